@@ -1,0 +1,135 @@
+"""Seeded synthetic inputs for the tests, the smoke check and the benchmark.
+
+This module only draws and lays out random inputs (numpy ``default_rng``
+streams; the 16- and 8-bit float inputs are rounded from float32 by torch's
+CPU conversions).  It holds none of the arithmetic of the elementwise or
+map-reduce method, and it is shared by both sides of every parity check: the
+same bytes go to the GPU library and to the CPU oracle.
+
+Workloads (the paper publishes no data sets; its listings use small random or
+``arange`` arrays, which the tests reuse):
+
+* ``dot_1m``: n = 2**20 float32 x, y ~ U[-1, 1], seed 0 -- one map-reduce dot.
+* ``plain_at_scale``: n = 2**28; x, y float32 ~ U[-1, 1] (seed 1),
+  k int32 ~ U{0 .. 2**20 - 1} (seed 2).
+* ``precision``: n = 2**27 values lognormal(0, 3) with random signs, and a
+  cancellation case [x; -x (1 + eps)], eps ~ U[-1e-3, 1e-3] (seed 3),
+  scaled by a power of two per format, rounded to float32 (the "original"
+  tensor) and then to bfloat16, half or FP8-E4M3 (saturating at 448).
+* ``segments``: 4096 segment lengths lognormal with median 2**12 and sigma
+  sqrt(2 ln 4) (so the mean is 2**14), rounded and clipped to [1, 2**20]
+  (seed 4), total 62,032,791; x, y float32 ~ U[-1, 1] drawn after the lengths.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+N_DOT = 1 << 20
+N_PLAIN = 1 << 28
+N_PRECISION = 1 << 27
+N_SEGMENTS = 4096
+
+E1 = ("float *z, const float *x, const float *y", "z[i] = 2.5f*x[i] - 0.5f*y[i]")
+E2 = ("float *z, const float *x, const float *y", "z[i] = sqrtf(x[i]*x[i] + y[i]*y[i])")
+R_COUNT = ("long: const int *k", "k[i] % 7 == 3", "a+b", "0")
+R_SUM = ("long: const int *k", "k[i]", "a+b", "0")
+R_MAX = ("float: const float *x", "x[i]", "max(a,b)", "-INFINITY")
+DOT = ("float: const float *x, const float *y", "x[i]*y[i]", "a+b", "0")
+
+
+def uniform_f32(rng, n, lo=-1.0, hi=1.0):
+    return rng.uniform(lo, hi, n).astype(np.float32)
+
+
+def dot_1m(n=N_DOT):
+    rng = np.random.default_rng(0)
+    x = uniform_f32(rng, n)
+    y = uniform_f32(rng, n)
+    return x, y
+
+
+def plain_xy(n=N_PLAIN):
+    rng = np.random.default_rng(1)
+    x = uniform_f32(rng, n)
+    y = uniform_f32(rng, n)
+    return x, y
+
+
+def plain_k(n=N_PLAIN):
+    rng = np.random.default_rng(2)
+    return rng.integers(0, 1 << 20, n, dtype=np.int32)
+
+
+# -------------------------------------------------------------- precision
+FMAX_SCALE = {"bfloat16": None, "float16": 2.0 ** 15, "fp8_e4m3": 448.0}
+
+
+def precision_values(n=N_PRECISION, case="lognormal"):
+    """float64 values of the precision workload (before any scaling)."""
+    rng = np.random.default_rng(3)
+    if case == "lognormal":
+        mag = rng.lognormal(0.0, 3.0, n)
+        sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+        return mag * sign
+    if case == "cancel":
+        h = n // 2
+        mag = rng.lognormal(0.0, 3.0, h)
+        sign = np.where(rng.random(h) < 0.5, -1.0, 1.0)
+        x = mag * sign
+        eps = rng.uniform(-1e-3, 1e-3, h)
+        return np.concatenate([x, -x * (1.0 + eps)])
+    raise ValueError(case)
+
+
+@dataclass
+class Quantized:
+    fmt: str                # 'bfloat16' | 'float16' | 'fp8_e4m3'
+    bits: np.ndarray        # raw storage (uint16 or uint8)
+    original: np.ndarray    # float32 values before rounding to fmt (already scaled)
+    scale: float            # power of two applied before rounding (value = stored / scale)
+
+
+def power_of_two_scale(fmt, values):
+    fmax = FMAX_SCALE[fmt]
+    if fmax is None:
+        return 1.0
+    amax = float(np.max(np.abs(values)))
+    if amax == 0.0:
+        return 1.0
+    return 2.0 ** math.floor(math.log2(fmax / amax))
+
+
+def quantize(fmt, values64):
+    import torch
+    scale = power_of_two_scale(fmt, values64)
+    original = (values64 * scale).astype(np.float32)
+    t = torch.from_numpy(original)
+    if fmt == "bfloat16":
+        bits = t.to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    elif fmt == "float16":
+        bits = t.to(torch.float16).view(torch.int16).numpy().view(np.uint16)
+    elif fmt == "fp8_e4m3":
+        bits = t.clamp(-448.0, 448.0).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    else:
+        raise ValueError(fmt)
+    return Quantized(fmt, bits.copy(), original, scale)
+
+
+# -------------------------------------------------------------- segments
+SEGMENT_SIGMA = math.sqrt(2.0 * math.log(4.0))
+
+
+def segments(nseg=N_SEGMENTS, median=4096.0, sigma=SEGMENT_SIGMA, max_len=1 << 20, seed=4):
+    rng = np.random.default_rng(seed)
+    lengths = np.clip(np.rint(rng.lognormal(math.log(median), sigma, nseg)), 1, max_len)
+    lengths = lengths.astype(np.int64)
+    offsets = np.zeros(nseg + 1, dtype=np.int64)
+    np.cumsum(lengths, out=offsets[1:])
+    total = int(offsets[-1])
+    x = uniform_f32(rng, total)
+    y = uniform_f32(rng, total)
+    return offsets, x, y
