@@ -1,0 +1,251 @@
+/*
+ * hipmr.h -- run-time generated elementwise and map-reduce kernels for the
+ * AMD Instinct MI355X (gfx950, CDNA4).  C ABI of libhipmr.so.
+ *
+ * Programming model (Kloeckner et al., "GPU Scripting and Code Generation
+ * with PyCUDA"):
+ *   - device code is given as C source text, not translated from the host
+ *     language (section "Core Method");
+ *   - an elementwise kernel is a C argument list plus a statement, or a
+ *     semicolon-separated list of statements, run for every value of the
+ *     formal index i over arrays of one common length (section "Efficient
+ *     Evaluation of Element-wise Expressions");
+ *   - a map-reduce kernel adds a result dtype, a map expression evaluated at
+ *     every i, a reduce expression in the formal arguments a and b, and a
+ *     neutral element, the identity of the reduce operation; the result stays
+ *     in device memory (section "Map-Reduce");
+ *   - generated sources are compiled on demand and cached, so that unchanged
+ *     kernels load without recompiling (section "Core Method", compilation
+ *     and caching figure); constants, types and trip counts are substituted
+ *     into the source at run time (section "Code Generation", subsections
+ *     "The Cost of Flexibility" and "Generating Code", textual keyword
+ *     replacement);
+ *   - errors surface as status codes with a message instead of requiring
+ *     explicit checks (section "The Basics of GPU programming").
+ *
+ * General conventions
+ *   - Every call returns HIPMR_OK (0) or a negative hipmr_status; the message
+ *     of the last failure on the calling thread is hipmr_last_error().  No
+ *     call aborts the process or throws across the ABI.
+ *   - "device pointer" means memory allocated on the current HIP device (for
+ *     example a torch tensor's data_ptr()).  The library never allocates,
+ *     frees or retains device memory: inputs, outputs and workspaces belong
+ *     to the caller and must stay valid until the work queued on the stream
+ *     has finished.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     GPU work is enqueued asynchronously on it; kernel faults surface at the
+ *     next synchronisation, as in HIP.
+ *   - args: an array with one entry per declared argument, in declaration
+ *     order; args[k] points to host storage holding the k-th argument's value
+ *     (the device pointer value for arrays, the scalar itself for scalars),
+ *     exactly like hipModuleLaunchKernel's kernelParams.  Values are copied
+ *     during the call.
+ *   - The library runs on the current HIP device of the calling thread; code
+ *     objects are loaded once per device.
+ */
+#ifndef HIPMR_H_
+#define HIPMR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hipmr_status;
+
+#define HIPMR_OK               0
+#define HIPMR_E_INVALID       -1  /* bad argument: NULL, n < 0, bad config, ... */
+#define HIPMR_E_PARSE         -2  /* signature or expression outside the grammar */
+#define HIPMR_E_COMPILE       -3  /* hipRTC rejected the generated source; log in last_error */
+#define HIPMR_E_HIP           -4  /* a HIP runtime call failed */
+#define HIPMR_E_MISMATCH      -5  /* argument does not match the handle (kind, map_expr, ...) */
+#define HIPMR_E_UNSUPPORTED   -6  /* valid C, but not supported by this variant */
+#define HIPMR_E_BUDGET        -7  /* serving: a job can never fit the memory budget */
+#define HIPMR_E_WORKSPACE     -8  /* workspace missing or smaller than required */
+
+/* Element types (dtype codes).  Spellings accepted in signatures:
+ *   float | double | int8_t, char, signed char | uint8_t, unsigned char |
+ *   int16_t, short | uint16_t, unsigned short | int32_t, int, signed |
+ *   uint32_t, unsigned, unsigned int | int64_t, long, long long |
+ *   bfloat16, __hip_bfloat16 | half, __half, float16 | fp8_e4m3
+ * bfloat16, half and fp8_e4m3 (OCP E4M3, "fn": no infinities, max 448) are
+ * storage types: a read converts exactly to float, and all arithmetic on
+ * them happens in float; a store rounds to nearest even (fp8 saturates to
+ * +-448). */
+#define HIPMR_F32   1
+#define HIPMR_F64   2
+#define HIPMR_I8    3
+#define HIPMR_U8    4
+#define HIPMR_I16   5
+#define HIPMR_U16   6
+#define HIPMR_I32   7
+#define HIPMR_U32   8
+#define HIPMR_I64   9
+#define HIPMR_BF16 10
+#define HIPMR_F16  11
+#define HIPMR_FP8  12
+
+typedef struct hipmr_kernel *hipmr_handle;
+
+/* Optional launch geometry; any field 0 means "library default".  Used by
+ * the *_ex calls, the autotuner and benchmarks (section "Automated Tuning":
+ * variants are kept and chosen at run time). */
+typedef struct hipmr_launch_config {
+    int32_t block;            /* threads per block: multiple of 64 in [64, 1024]       */
+    int32_t items_per_thread; /* vector chunks per thread per grid-stride pass: 1..16  */
+    int32_t grid;             /* blocks; 0: min(needed, blocks_per_cu * CU count)       */
+    int32_t blocks_per_cu;    /* cap used when grid == 0                                */
+    int32_t vec;              /* elements per vector chunk: 0 = 16 bytes of the narrowest
+                                 array; power of two 1..16                             */
+    int32_t flags;            /* HIPMR_CFG_* bits                                       */
+} hipmr_launch_config;
+
+#define HIPMR_CFG_NONTEMPORAL  1  /* streaming (non-temporal) loads and stores        */
+#define HIPMR_CFG_FORCE_SCALAR 2  /* use the one-element-per-step kernel variant      */
+#define HIPMR_CFG_TEMPORAL     4  /* force ordinary (temporal) loads and stores       */
+
+/* ------------------------------------------------------------------ core */
+
+/* Compiles (or finds in the cache) the kernels of one elementwise or map-reduce
+ * operation.  Section "Efficient Evaluation of Element-wise Expressions"
+ * (ElementwiseKernel(arguments, operation, name)) and section "Map-Reduce"
+ * (ReductionKernel(dtype_out, arguments, map_expr, ...)).
+ *   dtypes: "[result_type ':'] decl (',' decl)*", decl = "[const] type [*] name";
+ *           a leading "result_type:" makes a map-reduce handle (the paper puts
+ *           the result dtype first), otherwise an elementwise handle.
+ *   expr:   elementwise: the statement list over the formal index i (int when
+ *           n < 2^31, else 64-bit); the length is available as n.  Map-reduce:
+ *           the map expression.  Writes are supported to name[i] only.
+ *   name:   (compile_named) prefix of the generated kernel symbols, which are
+ *           extern "C" "<name>_<kind>_<hash8>"; default "hipmr".
+ *   *out:   receives a handle (reference counted; release with hipmr_release).
+ * The elementwise code object is built eagerly with hipRTC for gfx950 (no GPU
+ * is needed to compile); map-reduce kernels are built when the reduce
+ * expression is known (hipmr_prepare_reduce or the first hipmr_reduce).
+ * Errors: E_INVALID (NULL), E_PARSE (grammar; message names the position),
+ * E_UNSUPPORTED (e.g. return/goto, writes in a map), E_COMPILE (hipRTC log). */
+hipmr_status hipmr_compile(const char *expr, const char *dtypes, hipmr_handle *out);
+hipmr_status hipmr_compile_named(const char *expr, const char *dtypes, const char *name,
+                                 hipmr_handle *out);
+
+/* Runs an elementwise handle over i in [0, n).  Section "Efficient Evaluation
+ * of Element-wise Expressions" (one pass over all operands).  n == 0 enqueues
+ * nothing.  Arrays must hold at least n elements (the caller checks lengths).
+ * When every array is accessed only as name[i] and all array pointers share
+ * one misalignment, the 16-byte-vector kernel runs (unaligned head and ragged
+ * tail handled by scalar code); otherwise the one-element kernel.
+ * Errors: E_INVALID (n < 0, NULL args or array pointer), E_MISMATCH (reduce
+ * handle), E_COMPILE / E_HIP. */
+hipmr_status hipmr_elementwise(hipmr_handle h, int64_t n, void *const *args, void *stream);
+hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void *const *args,
+                                  const hipmr_launch_config *cfg, void *stream);
+
+/* Bytes of device workspace hipmr_reduce needs for n elements (depends only
+ * on the handle's result type and the device's CU count; a few tens of KiB).
+ * Returns 0 for an invalid handle. */
+size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n);
+
+/* Map-reduce: *out = neutral (+) map(0) (+) ... (+) map(n-1), (+) being
+ * combine_op.  Section "Map-Reduce" (reduction expression of formal arguments
+ * a and b, neutral element; result left on the GPU).
+ *   map_expr:   NULL or byte-equal to the handle's expression (E_MISMATCH).
+ *   combine_op: C expression in a and b of the result type, assumed
+ *               associative and commutative.  The spellings "a+b", "b+a",
+ *               "sum", "max(a,b)", "max(b,a)", "max", "min(a,b)", "min(b,a)",
+ *               "min" (blanks ignored) select specialised code; for float and
+ *               double max/min mean IEEE 754-2019 maximum/minimum (NaN
+ *               propagates, -0 < +0).
+ *   neutral:    C expression converted to the result type.
+ *   out:        device pointer to one element of the result type.
+ *   workspace:  device buffer of at least hipmr_reduce_workspace_bytes(h, n)
+ *               bytes (E_WORKSPACE otherwise); it is scratch for block partials.
+ * Two launches on stream (block partials, then one block folding them), no
+ * atomics; for a given device, n and launch configuration the result is
+ * bitwise reproducible.  n == 0 writes neutral.
+ * Errors: E_INVALID, E_MISMATCH (elementwise handle or map_expr), E_PARSE,
+ * E_COMPILE, E_WORKSPACE, E_HIP. */
+hipmr_status hipmr_reduce(hipmr_handle h, const char *map_expr, const char *combine_op,
+                          const char *neutral, int64_t n, void *const *args, void *out,
+                          void *workspace, size_t workspace_bytes, void *stream);
+hipmr_status hipmr_reduce_ex(hipmr_handle h, const char *map_expr, const char *combine_op,
+                             const char *neutral, int64_t n, void *const *args, void *out,
+                             void *workspace, size_t workspace_bytes,
+                             const hipmr_launch_config *cfg, void *stream);
+
+/* Builds the map-reduce kernels for (combine_op, neutral) ahead of the first
+ * hipmr_reduce (the paper's prepared invocation, section "The Basics of GPU
+ * programming", declares argument types once for later calls).  No GPU needed. */
+hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char *combine_op, const char *neutral);
+
+/* Message of the last failure on this thread ("" if none).  Owned by the
+ * library; valid until the next call on this thread. */
+const char *hipmr_last_error(void);
+
+/* Drops one reference; the handle must not be used afterwards.  Cached code
+ * objects stay in the process-wide cache. NULL is ignored. */
+void hipmr_release(hipmr_handle h);
+
+/* ------------------------------------------------------------------ introspection */
+
+typedef struct hipmr_handle_info {
+    int32_t is_reduce;      /* 1: map-reduce handle                                */
+    int32_t result_dtype;   /* HIPMR_* of the result (reduce), else 0              */
+    int32_t nargs;          /* declared arguments                                  */
+    int32_t vectorizable;   /* every array access is name[i]                       */
+    int32_t vec;            /* default elements per vector chunk                   */
+    uint32_t hash;          /* first 32 bits of the expression+signature hash      */
+} hipmr_handle_info;
+
+hipmr_status hipmr_get_handle_info(hipmr_handle h, hipmr_handle_info *info);
+
+/* Declared argument k: dtype (HIPMR_*), whether it is a pointer, declared
+ * const, read and/or written by the expression (as the classifier sees it). */
+hipmr_status hipmr_get_arg_info(hipmr_handle h, int32_t k, int32_t *dtype, int32_t *is_pointer,
+                                int32_t *is_const, int32_t *is_read, int32_t *is_written);
+
+/* Generated HIP source of one kernel variant (for inspection and tests).
+ *   kind: 0 elementwise (vector), 1 elementwise (scalar), 2 reduce stage 1
+ *         (vector), 3 reduce stage 1 (scalar), 4 reduce stage 2.
+ *   combine_op/neutral: required for kinds 2-4.
+ * Copies at most cap bytes including the terminating NUL; *len gets the full
+ * length (without NUL). */
+hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char *combine_op,
+                                     const char *neutral, char *buf, size_t cap, size_t *len);
+
+/* Compile-cache counters (process-wide).  Section "Core Method": a source
+ * already compiled is found in memory or in the on-disk cache
+ * ($HIPMR_CACHE_DIR, default $XDG_CACHE_HOME/hipmr or ~/.cache/hipmr) instead
+ * of recompiling. */
+typedef struct hipmr_cache_stats {
+    uint64_t memory_hits;
+    uint64_t disk_hits;
+    uint64_t compiles;
+    uint64_t disk_rejects;     /* corrupt or truncated cache files rebuilt        */
+    double   compile_ms;       /* wall time spent in hipRTC                       */
+} hipmr_cache_stats;
+
+hipmr_status hipmr_get_cache_stats(hipmr_cache_stats *out);
+
+/* Forgets the in-memory cache of code objects (handles stay valid and reload
+ * from the disk cache or recompile on next use).  For tests of the disk cache. */
+void hipmr_cache_drop_memory(void);
+
+/* Hex SHA-256 (FIPS 180-4) of a byte string, the function behind cache keys.
+ * out must hold 65 bytes. */
+hipmr_status hipmr_sha256_hex(const void *data, size_t len, char *out);
+
+/* Size in bytes of a dtype code, 0 if unknown. */
+int32_t hipmr_dtype_size(int32_t dtype);
+
+/* Compiles a representative set of kernel variants of every template with
+ * hipRTC (no GPU needed); returns the number compiled in *count.  A build
+ * check of the device templates. */
+hipmr_status hipmr_selftest_compile(int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPMR_H_ */

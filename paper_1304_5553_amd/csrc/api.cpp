@@ -1,0 +1,477 @@
+// The C ABI: handles, argument marshalling, launch geometry and the two
+// launch sequences (elementwise; map-reduce = block partials + final fold).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cctype>
+#include <cstring>
+#include <map>
+
+#include "common.h"
+
+using namespace hipmr;
+
+struct hipmr_kernel {
+    std::atomic<int> refs{1};
+    Program prog;
+    int default_vec = 4;
+    std::mutex mu;
+    std::map<std::string, std::shared_ptr<CodeObject>> variants;
+};
+
+namespace {
+
+constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
+constexpr int kStage2Block = 256;
+
+// default geometry (overridable per call through hipmr_launch_config)
+constexpr int kEwBlock = 256, kEwIpt = 4, kRedBlock = 256, kRedIpt = 8, kBlocksPerCu = 8;
+
+int default_vec_for(const Signature& sig) {
+    int min_size = 0;
+    for (auto& a : sig.args)
+        if (a.pointer && (a.read || a.written)) {
+            int s = dtype_size(a.dtype);
+            if (min_size == 0 || s < min_size) min_size = s;
+        }
+    if (min_size == 0) return 4;
+    return 16 / min_size;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int vec, LaunchCfg* out) {
+    *out = LaunchCfg();
+    out->block = block;
+    out->ipt = ipt;
+    out->vec = vec;
+    out->blocks_per_cu = kBlocksPerCu;
+    if (!c) return HIPMR_OK;
+    if (c->block) {
+        if (c->block < 64 || c->block > 1024 || c->block % 64)
+            return fail(HIPMR_E_INVALID, "launch config: block must be a multiple of 64 in [64, 1024]");
+        out->block = c->block;
+    }
+    if (c->items_per_thread) {
+        if (c->items_per_thread < 1 || c->items_per_thread > 16)
+            return fail(HIPMR_E_INVALID, "launch config: items_per_thread must be in [1, 16]");
+        out->ipt = c->items_per_thread;
+    }
+    if (c->vec) {
+        if (!is_pow2(c->vec) || c->vec > 16)
+            return fail(HIPMR_E_INVALID, "launch config: vec must be a power of two <= 16");
+        out->vec = c->vec;
+    }
+    if (c->grid < 0 || c->blocks_per_cu < 0)
+        return fail(HIPMR_E_INVALID, "launch config: negative grid or blocks_per_cu");
+    out->grid = c->grid;
+    if (c->blocks_per_cu) out->blocks_per_cu = c->blocks_per_cu;
+    if (c->flags & HIPMR_CFG_TEMPORAL) out->nontemporal = false;
+    if (c->flags & HIPMR_CFG_NONTEMPORAL) out->nontemporal = true;
+    out->force_scalar = (c->flags & HIPMR_CFG_FORCE_SCALAR) != 0;
+    return HIPMR_OK;
+}
+
+std::string spec_key(const KernelSpec& s) {
+    return std::to_string((int)s.kind) + "|" + std::to_string(s.idx64) + "|" +
+           std::to_string(s.block) + "|" + std::to_string(s.ipt) + "|" + std::to_string(s.vec) +
+           "|" + std::to_string(s.nontemporal) + "|" + s.combine + "\x1f" + s.neutral;
+}
+
+hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out) {
+    std::string k = spec_key(spec);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->variants.find(k);
+        if (it != h->variants.end()) {
+            *out = it->second;
+            return HIPMR_OK;
+        }
+    }
+    std::string symbol;
+    std::string src = render(h->prog, spec, &symbol);
+    hipmr_status st;
+    auto co = get_or_build(src, symbol, &st);
+    if (!co) return st;
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->variants[k] = co;
+    *out = co;
+    return HIPMR_OK;
+}
+
+hipmr_status variant_function(hipmr_kernel* h, const KernelSpec& spec, void** fn) {
+    std::shared_ptr<CodeObject> co;
+    hipmr_status st = get_variant(h, spec, &co);
+    if (st != HIPMR_OK) return st;
+    return get_function(*co, fn);
+}
+
+// Element offset "head" at which every accessed array is aligned for the
+// vector chunk loads; -1 if no common offset exists.
+long long common_head(const hipmr_kernel* h, void* const* args, int vec) {
+    for (int head = 0; head < vec; ++head) {
+        bool ok = true;
+        for (size_t k = 0; k < h->prog.sig.args.size() && ok; ++k) {
+            const ArgDecl& a = h->prog.sig.args[k];
+            if (!a.pointer || !(a.read || a.written)) continue;
+            uintptr_t p = (uintptr_t)(*(void* const*)args[k]);
+            int s = dtype_size(a.dtype);
+            uintptr_t align = (uintptr_t)std::min(vec * s, 16);
+            if (p % (uintptr_t)s != 0 || (p + (uintptr_t)head * s) % align != 0) ok = false;
+        }
+        if (ok) return head;
+    }
+    return -1;
+}
+
+hipmr_status check_args(hipmr_kernel* h, int64_t n, void* const* args) {
+    if (!h) return fail(HIPMR_E_INVALID, "NULL handle");
+    if (n < 0) return fail(HIPMR_E_INVALID, "n must be >= 0");
+    const auto& decl = h->prog.sig.args;
+    if (!decl.empty() && !args) return fail(HIPMR_E_INVALID, "args is NULL");
+    for (size_t k = 0; k < decl.size(); ++k) {
+        if (!args[k]) return fail(HIPMR_E_INVALID, "args[" + std::to_string(k) + "] is NULL");
+        if (decl[k].pointer && n > 0 && (decl[k].read || decl[k].written) &&
+            *(void* const*)args[k] == nullptr)
+            return fail(HIPMR_E_INVALID, "array argument '" + decl[k].name + "' is NULL");
+    }
+    return HIPMR_OK;
+}
+
+int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap) {
+    if (cfg.grid > 0) return std::min(cfg.grid, cap);
+    long long need = (work_units + per_block - 1) / per_block;
+    long long limit = (long long)cfg.blocks_per_cu * device_cu_count();
+    long long g = std::min(need, limit);
+    g = std::min<long long>(g, cap);
+    return (int)std::max<long long>(g, 1);
+}
+
+hipmr_status make_handle(const char* expr, const char* dtypes, const char* name,
+                         hipmr_handle* out) {
+    if (!expr || !dtypes || !out) return fail(HIPMR_E_INVALID, "NULL argument to hipmr_compile");
+    *out = nullptr;
+    std::string nm = name && *name ? name : "hipmr";
+    for (char c : nm)
+        if (!(std::isalnum((unsigned char)c) || c == '_'))
+            return fail(HIPMR_E_INVALID, "kernel name must be a C identifier");
+    auto h = std::make_unique<hipmr_kernel>();
+    h->prog.name = nm;
+    h->prog.expr = expr;
+    hipmr_status st = parse_signature(dtypes, &h->prog.sig);
+    if (st != HIPMR_OK) return st;
+    st = lex(expr, &h->prog.toks);
+    if (st != HIPMR_OK) return st;
+    if (h->prog.toks.size() <= 1) return fail(HIPMR_E_PARSE, "empty expression");
+    st = classify(h->prog.toks, &h->prog.sig, h->prog.sig.is_reduce, &h->prog.info);
+    if (st != HIPMR_OK) return st;
+    if (h->prog.sig.is_reduce) {
+        DType r = h->prog.sig.result;
+        if (!(r == DT_F32 || r == DT_F64 || r == DT_I32 || r == DT_U32 || r == DT_I64))
+            return fail(HIPMR_E_UNSUPPORTED, "reduce result type must be float, double, int, "
+                                             "unsigned or a 64-bit integer");
+    }
+    h->default_vec = default_vec_for(h->prog.sig);
+    if (!h->prog.sig.is_reduce) {
+        // build the default variant now so that errors surface at compile time
+        KernelSpec spec;
+        spec.kind = h->prog.info.vectorizable ? KernelKind::EwVector : KernelKind::EwScalar;
+        spec.block = kEwBlock;
+        spec.ipt = kEwIpt;
+        spec.vec = h->default_vec;
+        std::shared_ptr<CodeObject> co;
+        st = get_variant(h.get(), spec, &co);
+        if (st != HIPMR_OK) return st;
+    }
+    *out = h.release();
+    return HIPMR_OK;
+}
+
+KernelSpec s1_spec(const hipmr_kernel* h, bool vector, const LaunchCfg& cfg, bool idx64,
+                   const char* combine, const char* neutral) {
+    KernelSpec s;
+    s.kind = vector ? KernelKind::RedS1Vector : KernelKind::RedS1Scalar;
+    s.idx64 = idx64;
+    s.block = cfg.block;
+    s.ipt = cfg.ipt;
+    s.vec = vector ? cfg.vec : 1;
+    s.nontemporal = cfg.nontemporal;
+    s.combine = combine;
+    s.neutral = neutral;
+    return s;
+}
+
+KernelSpec s2_spec(const char* combine, const char* neutral) {
+    KernelSpec s;
+    s.kind = KernelKind::RedS2;
+    s.block = kStage2Block;
+    s.ipt = 1;
+    s.vec = 1;
+    s.combine = combine;
+    s.neutral = neutral;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+hipmr_status hipmr_compile(const char* expr, const char* dtypes, hipmr_handle* out) {
+    clear_error();
+    return make_handle(expr, dtypes, nullptr, out);
+}
+
+hipmr_status hipmr_compile_named(const char* expr, const char* dtypes, const char* name,
+                                 hipmr_handle* out) {
+    clear_error();
+    return make_handle(expr, dtypes, name, out);
+}
+
+hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void* const* args,
+                                  const hipmr_launch_config* cfgp, void* stream) {
+    clear_error();
+    hipmr_status st = check_args(h, n, args);
+    if (st != HIPMR_OK) return st;
+    if (h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "map-reduce handle passed to hipmr_elementwise");
+    LaunchCfg cfg;
+    st = resolve_cfg(cfgp, kEwBlock, kEwIpt, h->default_vec, &cfg);
+    if (st != HIPMR_OK) return st;
+    if (n == 0) return HIPMR_OK;
+    long long head = -1;
+    bool vector = h->prog.info.vectorizable && !cfg.force_scalar;
+    if (vector) head = common_head(h, args, cfg.vec);
+    if (head < 0) vector = false;
+    KernelSpec spec;
+    spec.kind = vector ? KernelKind::EwVector : KernelKind::EwScalar;
+    spec.idx64 = n >= (int64_t(1) << 31);
+    spec.block = cfg.block;
+    spec.ipt = cfg.ipt;
+    spec.vec = vector ? cfg.vec : 1;
+    spec.nontemporal = cfg.nontemporal;
+    void* fn = nullptr;
+    st = variant_function(h, spec, &fn);
+    if (st != HIPMR_OK) return st;
+    long long n64 = n, head64 = vector ? head : 0;
+    long long units = vector ? (n64 > head64 ? (n64 - head64) / cfg.vec : 0) : n64;
+    int grid = grid_for(units, cfg.block * (vector ? cfg.ipt : 1), cfg, 1 << 30);
+    std::vector<void*> params;
+    if (h->prog.sig.args.empty()) params.push_back(&head64);   // hipmr_unused
+    for (size_t k = 0; k < h->prog.sig.args.size(); ++k) params.push_back(args[k]);
+    params.push_back(&n64);
+    params.push_back(&head64);
+    return launch(fn, (unsigned)grid, (unsigned)cfg.block, params.data(), stream);
+}
+
+hipmr_status hipmr_elementwise(hipmr_handle h, int64_t n, void* const* args, void* stream) {
+    return hipmr_elementwise_ex(h, n, args, nullptr, stream);
+}
+
+size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n) {
+    (void)n;
+    if (!h || !h->prog.sig.is_reduce) return 0;
+    return (size_t)kMaxPartials * 8;
+}
+
+hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char* combine, const char* neutral) {
+    clear_error();
+    if (!h || !combine || !neutral) return fail(HIPMR_E_INVALID, "NULL argument");
+    if (!h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "elementwise handle");
+    LaunchCfg cfg;
+    resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, &cfg);
+    std::shared_ptr<CodeObject> co;
+    hipmr_status st = get_variant(h, s1_spec(h, h->prog.info.vectorizable, cfg, false, combine, neutral), &co);
+    if (st != HIPMR_OK) return st;
+    return get_variant(h, s2_spec(combine, neutral), &co);
+}
+
+hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* combine,
+                             const char* neutral, int64_t n, void* const* args, void* out,
+                             void* workspace, size_t workspace_bytes,
+                             const hipmr_launch_config* cfgp, void* stream) {
+    clear_error();
+    hipmr_status st = check_args(h, n, args);
+    if (st != HIPMR_OK) return st;
+    if (!h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "elementwise handle passed to hipmr_reduce");
+    if (map_expr && h->prog.expr != map_expr)
+        return fail(HIPMR_E_MISMATCH, "map_expr differs from the handle's expression");
+    if (!combine || !neutral) return fail(HIPMR_E_INVALID, "combine_op and neutral are required");
+    if (!out) return fail(HIPMR_E_INVALID, "out is NULL");
+    if (!workspace || workspace_bytes < hipmr_reduce_workspace_bytes(h, n))
+        return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_reduce_workspace_bytes()");
+    LaunchCfg cfg;
+    st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, &cfg);
+    if (st != HIPMR_OK) return st;
+
+    long long n64 = n, head64 = 0;
+    int grid = 0;
+    if (n > 0) {
+        long long head = -1;
+        bool vector = h->prog.info.vectorizable && !cfg.force_scalar;
+        if (vector) head = common_head(h, args, cfg.vec);
+        if (head < 0) vector = false;
+        head64 = vector ? head : 0;
+        void* fn = nullptr;
+        st = variant_function(h, s1_spec(h, vector, cfg, n >= (int64_t(1) << 31), combine, neutral), &fn);
+        if (st != HIPMR_OK) return st;
+        long long units = vector ? (n64 > head64 ? (n64 - head64) / cfg.vec : 0) : n64;
+        grid = grid_for(units, cfg.block * (vector ? cfg.ipt : 1), cfg, kMaxPartials);
+        std::vector<void*> params;
+        if (h->prog.sig.args.empty()) params.push_back(&head64);   // hipmr_unused
+        for (size_t k = 0; k < h->prog.sig.args.size(); ++k) params.push_back(args[k]);
+        params.push_back(&n64);
+        params.push_back(&head64);
+        params.push_back(&workspace);
+        st = launch(fn, (unsigned)grid, (unsigned)cfg.block, params.data(), stream);
+        if (st != HIPMR_OK) return st;
+    }
+    void* fn2 = nullptr;
+    st = variant_function(h, s2_spec(combine, neutral), &fn2);
+    if (st != HIPMR_OK) return st;
+    void* params2[3] = {&workspace, &grid, &out};
+    return launch(fn2, 1, kStage2Block, params2, stream);
+}
+
+hipmr_status hipmr_reduce(hipmr_handle h, const char* map_expr, const char* combine,
+                          const char* neutral, int64_t n, void* const* args, void* out,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+    return hipmr_reduce_ex(h, map_expr, combine, neutral, n, args, out, workspace,
+                           workspace_bytes, nullptr, stream);
+}
+
+const char* hipmr_last_error(void) { return last_error(); }
+
+void hipmr_release(hipmr_handle h) {
+    if (h && h->refs.fetch_sub(1) == 1) delete h;
+}
+
+hipmr_status hipmr_get_handle_info(hipmr_handle h, hipmr_handle_info* info) {
+    clear_error();
+    if (!h || !info) return fail(HIPMR_E_INVALID, "NULL argument");
+    info->is_reduce = h->prog.sig.is_reduce;
+    info->result_dtype = h->prog.sig.result;
+    info->nargs = (int32_t)h->prog.sig.args.size();
+    info->vectorizable = h->prog.info.vectorizable;
+    info->vec = h->default_vec;
+    std::string key = h->prog.expr + "\x1f" + std::to_string(h->prog.sig.args.size());
+    std::string hex = sha256_hex(key.data(), key.size());
+    info->hash = (uint32_t)std::stoul(hex.substr(0, 8), nullptr, 16);
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_get_arg_info(hipmr_handle h, int32_t k, int32_t* dtype, int32_t* is_pointer,
+                                int32_t* is_const, int32_t* is_read, int32_t* is_written) {
+    clear_error();
+    if (!h) return fail(HIPMR_E_INVALID, "NULL handle");
+    if (k < 0 || k >= (int32_t)h->prog.sig.args.size()) return fail(HIPMR_E_INVALID, "argument index out of range");
+    const ArgDecl& a = h->prog.sig.args[k];
+    if (dtype) *dtype = a.dtype;
+    if (is_pointer) *is_pointer = a.pointer;
+    if (is_const) *is_const = a.is_const;
+    if (is_read) *is_read = a.read;
+    if (is_written) *is_written = a.written;
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char* combine,
+                                     const char* neutral, char* buf, size_t cap, size_t* len) {
+    clear_error();
+    if (!h) return fail(HIPMR_E_INVALID, "NULL handle");
+    if (kind < 0 || kind > 4) return fail(HIPMR_E_INVALID, "kind must be in 0..4");
+    bool red = kind >= 2;
+    if (red != (bool)h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "kind does not match the handle");
+    if (red && (!combine || !neutral)) return fail(HIPMR_E_INVALID, "combine_op and neutral are required");
+    LaunchCfg cfg;
+    resolve_cfg(nullptr, red ? kRedBlock : kEwBlock, red ? kRedIpt : kEwIpt, h->default_vec, &cfg);
+    KernelSpec spec;
+    if (kind == 4) {
+        spec = s2_spec(combine, neutral);
+    } else if (red) {
+        spec = s1_spec(h, kind == 2, cfg, false, combine, neutral);
+    } else {
+        spec.kind = (KernelKind)kind;
+        spec.block = cfg.block;
+        spec.ipt = cfg.ipt;
+        spec.vec = kind == 0 ? cfg.vec : 1;
+    }
+    std::string sym;
+    std::string src = render(h->prog, spec, &sym);
+    if (len) *len = src.size();
+    if (buf && cap) {
+        size_t c = std::min(cap - 1, src.size());
+        std::memcpy(buf, src.data(), c);
+        buf[c] = '\0';
+    }
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_get_cache_stats(hipmr_cache_stats* out) {
+    clear_error();
+    if (!out) return fail(HIPMR_E_INVALID, "NULL argument");
+    cache_stats(out);
+    return HIPMR_OK;
+}
+
+void hipmr_cache_drop_memory(void) { cache_drop_memory(); }
+
+hipmr_status hipmr_sha256_hex(const void* data, size_t len, char* out) {
+    clear_error();
+    if ((!data && len) || !out) return fail(HIPMR_E_INVALID, "NULL argument");
+    std::string h = sha256_hex(data, len);
+    std::memcpy(out, h.c_str(), 65);
+    return HIPMR_OK;
+}
+
+int32_t hipmr_dtype_size(int32_t dtype) { return dtype_size((DType)dtype); }
+
+hipmr_status hipmr_selftest_compile(int32_t* count) {
+    clear_error();
+    struct Case { const char* expr; const char* dtypes; const char* combine; const char* neutral; };
+    static const Case cases[] = {
+        {"z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y", nullptr, nullptr},
+        {"z[i] = sqrtf(x[i]*x[i] + y[i]*y[i])", "float *z, const float *x, const float *y", nullptr, nullptr},
+        {"if (k[i] > 3) o[i] = x[i]; else o[i] += 1", "const int *k, const bfloat16 *x, half *o", nullptr, nullptr},
+        {"q[i] = x[i + 1 < n ? i + 1 : i] * s", "fp8_e4m3 *q, const float *x, float s", nullptr, nullptr},
+        {"k[i] % 7 == 3", "long: const int *k", "a+b", "0"},
+        {"x[i]*y[i]", "float: const float *x, const float *y", "a+b", "0"},
+        {"x[i]", "float: const float *x", "max(a,b)", "-INFINITY"},
+        {"x[i]", "double: const fp8_e4m3 *x", "min", "INFINITY"},
+        {"k[i]", "unsigned: const unsigned *k", "a|b", "0u"},
+        {"x[n - 1 - i]", "float: const float *x", "a+b", "0"},
+    };
+    int32_t built = 0;
+    for (const Case& c : cases) {
+        hipmr_handle h = nullptr;
+        hipmr_status st = make_handle(c.expr, c.dtypes, "selftest", &h);
+        if (st != HIPMR_OK) return st;
+        std::shared_ptr<CodeObject> co;
+        if (h->prog.sig.is_reduce) {
+            LaunchCfg cfg;
+            resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, &cfg);
+            for (bool vector : {true, false}) {
+                if (vector && !h->prog.info.vectorizable) continue;
+                for (bool idx64 : {false, true}) {
+                    st = get_variant(h, s1_spec(h, vector, cfg, idx64, c.combine, c.neutral), &co);
+                    if (st != HIPMR_OK) { hipmr_release(h); return st; }
+                    ++built;
+                }
+            }
+            st = get_variant(h, s2_spec(c.combine, c.neutral), &co);
+            ++built;
+        } else {
+            KernelSpec spec;
+            spec.kind = KernelKind::EwScalar;
+            spec.block = kEwBlock;
+            spec.ipt = kEwIpt;
+            spec.vec = 1;
+            st = get_variant(h, spec, &co);
+            built += 2;   // + the vector/scalar default built by make_handle
+        }
+        hipmr_release(h);
+        if (st != HIPMR_OK) return st;
+    }
+    if (count) *count = built;
+    return HIPMR_OK;
+}
+
+}  // extern "C"

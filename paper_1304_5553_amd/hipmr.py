@@ -1,0 +1,410 @@
+"""Python binding of libhipmr.so (ctypes): argument marshalling only.
+
+Every step of the elementwise / map-reduce path runs in the library's
+run-time generated HIP kernels; this module turns torch tensors and Python
+scalars into the C ABI's ``void *args[]`` and maps status codes to
+exceptions (the paper raises exceptions instead of requiring explicit error
+checks, section "The Basics of GPU programming").  If the shared library is
+missing, importing the binding's entry points raises: there is no fallback.
+
+Calls of the C ABI keep their names: ``compile``, ``elementwise``,
+``reduce``, ... .  On top sit the paper's two classes,
+``ElementwiseKernel(arguments, operation, name)`` and
+``ReductionKernel(dtype_out, arguments, map_expr, reduce_expr, neutral)``
+(section "Efficient Evaluation of Element-wise Expressions" and section
+"Map-Reduce").
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhipmr.so")
+
+OK = 0
+F32, F64, I8, U8, I16, U16, I32, U32, I64, BF16, F16, FP8 = range(1, 13)
+DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "int16_t",
+               U16: "uint16_t", I32: "int", U32: "unsigned", I64: "int64_t",
+               BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3"}
+
+CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
+
+
+class HipmrError(RuntimeError):
+    code = None
+
+    def __init__(self, message, code=None):
+        super().__init__(message)
+        if code is not None:
+            self.code = code
+
+
+class InvalidError(HipmrError, ValueError):
+    code = -1
+
+
+class ParseError(HipmrError, ValueError):
+    code = -2
+
+
+class CompileError(HipmrError):
+    code = -3
+
+
+class HipError(HipmrError):
+    code = -4
+
+
+class MismatchError(HipmrError, ValueError):
+    code = -5
+
+
+class UnsupportedError(HipmrError):
+    code = -6
+
+
+class BudgetError(HipmrError):
+    code = -7
+
+
+class WorkspaceError(HipmrError, ValueError):
+    code = -8
+
+
+_ERRORS = {c.code: c for c in (InvalidError, ParseError, CompileError, HipError, MismatchError,
+                               UnsupportedError, BudgetError, WorkspaceError)}
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("vec", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class HandleInfo(ctypes.Structure):
+    _fields_ = [("is_reduce", ctypes.c_int32), ("result_dtype", ctypes.c_int32),
+                ("nargs", ctypes.c_int32), ("vectorizable", ctypes.c_int32),
+                ("vec", ctypes.c_int32), ("hash", ctypes.c_uint32)]
+
+
+class CacheStats(ctypes.Structure):
+    _fields_ = [("memory_hits", ctypes.c_uint64), ("disk_hits", ctypes.c_uint64),
+                ("compiles", ctypes.c_uint64), ("disk_rejects", ctypes.c_uint64),
+                ("compile_ms", ctypes.c_double)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+_VP, _SZ, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_CP = ctypes.c_char_p
+_SIGS = {
+    "hipmr_compile": (_I32, [_CP, _CP, ctypes.POINTER(_VP)]),
+    "hipmr_compile_named": (_I32, [_CP, _CP, _CP, ctypes.POINTER(_VP)]),
+    "hipmr_elementwise": (_I32, [_VP, _I64, _VP, _VP]),
+    "hipmr_elementwise_ex": (_I32, [_VP, _I64, _VP, ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_reduce_workspace_bytes": (_SZ, [_VP, _I64]),
+    "hipmr_reduce": (_I32, [_VP, _CP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ, _VP]),
+    "hipmr_reduce_ex": (_I32, [_VP, _CP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ,
+                               ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_prepare_reduce": (_I32, [_VP, _CP, _CP]),
+    "hipmr_last_error": (_CP, []),
+    "hipmr_release": (None, [_VP]),
+    "hipmr_get_handle_info": (_I32, [_VP, ctypes.POINTER(HandleInfo)]),
+    "hipmr_get_arg_info": (_I32, [_VP, _I32] + [ctypes.POINTER(_I32)] * 5),
+    "hipmr_get_kernel_source": (_I32, [_VP, _I32, _CP, _CP, _CP, _SZ, ctypes.POINTER(_SZ)]),
+    "hipmr_get_cache_stats": (_I32, [ctypes.POINTER(CacheStats)]),
+    "hipmr_cache_drop_memory": (None, []),
+    "hipmr_sha256_hex": (_I32, [_VP, _SZ, _CP]),
+    "hipmr_dtype_size": (_I32, [_I32]),
+    "hipmr_selftest_compile": (_I32, [ctypes.POINTER(_I32)]),
+}
+
+
+def lib():
+    """The loaded shared library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        with _lib_lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError(
+                        f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                        "(make -C paper_1304_5553_amd/csrc); there is no fallback path")
+                handle = ctypes.CDLL(LIB_PATH)
+                for name, (res, args) in _SIGS.items():
+                    fn = getattr(handle, name)
+                    fn.restype = res
+                    fn.argtypes = args
+                _lib = handle
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        msg = lib().hipmr_last_error().decode(errors="replace")
+        raise _ERRORS.get(status, HipmrError)(msg, status)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _config(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, LaunchConfig):
+        return ctypes.byref(cfg)
+    c = LaunchConfig()
+    for k, v in dict(cfg).items():
+        setattr(c, k, int(v))
+    return ctypes.byref(c)
+
+
+_CTYPE = {F32: ctypes.c_float, F64: ctypes.c_double, I8: ctypes.c_int8, U8: ctypes.c_uint8,
+          I16: ctypes.c_int16, U16: ctypes.c_uint16, I32: ctypes.c_int32, U32: ctypes.c_uint32,
+          I64: ctypes.c_int64, BF16: ctypes.c_uint16, F16: ctypes.c_uint16, FP8: ctypes.c_uint8}
+
+
+def torch_dtype(code):
+    import torch
+    return {F32: torch.float32, F64: torch.float64, I8: torch.int8, U8: torch.uint8,
+            I16: torch.int16, U16: torch.uint16, I32: torch.int32, U32: torch.uint32,
+            I64: torch.int64, BF16: torch.bfloat16, F16: torch.float16,
+            FP8: torch.float8_e4m3fn}[code]
+
+
+def _lowp_bits(code, value):
+    """Bit pattern of a Python number rounded to bfloat16 / half / fp8."""
+    import torch
+    t = torch.tensor([float(value)], dtype=torch.float32)
+    if code == FP8:
+        return int(t.clamp(-448, 448).to(torch.float8_e4m3fn).view(torch.uint8).item())
+    return int(t.to(torch_dtype(code)).view(torch.int16).item()) & 0xFFFF
+
+
+class Arg:
+    __slots__ = ("name", "dtype", "pointer", "const", "read", "written")
+
+
+class Kernel:
+    """A compiled handle (the C ABI's hipmr_handle)."""
+
+    def __init__(self, expr, dtypes, name=None):
+        self.expr = expr
+        self.dtypes = dtypes
+        h = _VP()
+        if name is None:
+            _check(lib().hipmr_compile(expr.encode(), dtypes.encode(), ctypes.byref(h)))
+        else:
+            _check(lib().hipmr_compile_named(expr.encode(), dtypes.encode(), name.encode(),
+                                             ctypes.byref(h)))
+        self._h = h
+        info = HandleInfo()
+        _check(lib().hipmr_get_handle_info(h, ctypes.byref(info)))
+        self.is_reduce = bool(info.is_reduce)
+        self.result_dtype = info.result_dtype
+        self.vectorizable = bool(info.vectorizable)
+        self.vec = info.vec
+        self.args = []
+        for k in range(info.nargs):
+            vals = [_I32() for _ in range(5)]
+            _check(lib().hipmr_get_arg_info(h, k, *[ctypes.byref(v) for v in vals]))
+            a = Arg()
+            a.dtype, a.pointer, a.const, a.read, a.written = (v.value for v in vals)
+            self.args.append(a)
+        names = [d.strip().replace("*", " ").split()[-1]
+                 for d in dtypes.split(":", 1)[-1].split(",") if d.strip()]
+        for a, nm in zip(self.args, names):
+            a.name = nm
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hipmr_release(h)
+            self._h = None
+
+    def marshal(self, args):
+        """(keep-alive list, ctypes array of pointers) for the C ABI's args."""
+        if len(args) != len(self.args):
+            raise InvalidError(f"expected {len(self.args)} arguments, got {len(args)}")
+        keep = []
+        ptrs = (ctypes.c_void_p * max(1, len(args)))()
+        for k, (decl, val) in enumerate(zip(self.args, args)):
+            if decl.pointer:
+                p = val if isinstance(val, int) else (0 if val is None else val.data_ptr())
+                c = ctypes.c_void_p(p)
+            elif decl.dtype in (BF16, F16, FP8):
+                c = _CTYPE[decl.dtype](_lowp_bits(decl.dtype, val))
+            else:
+                c = _CTYPE[decl.dtype](val)
+            keep.append(c)
+            ptrs[k] = ctypes.cast(ctypes.byref(c), ctypes.c_void_p)
+        return keep, ptrs
+
+    def source(self, kind, combine_op=None, neutral=None):
+        ln = ctypes.c_size_t()
+        _check(lib().hipmr_get_kernel_source(self._h, kind, _enc(combine_op), _enc(neutral),
+                                             None, 0, ctypes.byref(ln)))
+        buf = ctypes.create_string_buffer(ln.value + 1)
+        _check(lib().hipmr_get_kernel_source(self._h, kind, _enc(combine_op), _enc(neutral),
+                                             buf, len(buf), ctypes.byref(ln)))
+        return buf.value.decode()
+
+
+def _enc(s):
+    return None if s is None else s.encode()
+
+
+# --------------------------------------------------------------- C ABI names
+def compile(expr, dtypes, name=None) -> Kernel:   # noqa: A001 - the C ABI's name
+    return Kernel(expr, dtypes, name)
+
+
+def elementwise(handle: Kernel, n, args, stream=None, config=None):
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_elementwise_ex(handle.handle, int(n), ptrs, _config(config),
+                                      _stream_ptr(stream)))
+    return keep
+
+
+_ws_cache = {}
+_ws_lock = threading.Lock()
+
+
+def workspace(nbytes, device, stream_ptr):
+    """A device workspace of at least nbytes, cached per (device, stream)."""
+    import torch
+    key = (str(device), stream_ptr)
+    with _ws_lock:
+        buf = _ws_cache.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+            _ws_cache[key] = buf
+        return buf
+
+
+def reduce_workspace_bytes(handle: Kernel, n):
+    return lib().hipmr_reduce_workspace_bytes(handle.handle, int(n))
+
+
+def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspace_buf=None,
+           stream=None, config=None):   # noqa: A001 - the C ABI's name
+    s = _stream_ptr(stream)
+    need = reduce_workspace_bytes(handle, n)
+    if workspace_buf is None:
+        workspace_buf = workspace(need, out.device, s)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_reduce_ex(handle.handle, _enc(map_expr), _enc(combine_op), _enc(neutral),
+                                 int(n), ptrs, ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(workspace_buf.data_ptr()),
+                                 workspace_buf.numel() * workspace_buf.element_size(),
+                                 _config(config), s))
+    return out
+
+
+def prepare_reduce(handle: Kernel, combine_op, neutral):
+    _check(lib().hipmr_prepare_reduce(handle.handle, combine_op.encode(), neutral.encode()))
+
+
+def cache_stats():
+    s = CacheStats()
+    _check(lib().hipmr_get_cache_stats(ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in CacheStats._fields_}
+
+
+def cache_drop_memory():
+    lib().hipmr_cache_drop_memory()
+
+
+def sha256_hex(data: bytes) -> str:
+    out = ctypes.create_string_buffer(65)
+    _check(lib().hipmr_sha256_hex(data, len(data), out))
+    return out.value.decode()
+
+
+def selftest_compile() -> int:
+    n = _I32()
+    _check(lib().hipmr_selftest_compile(ctypes.byref(n)))
+    return n.value
+
+
+# --------------------------------------------------------------- paper classes
+def _tensor_args(kernel, args):
+    import torch
+    n = None
+    for decl, a in zip(kernel.args, args):
+        if decl.pointer:
+            if not isinstance(a, torch.Tensor):
+                raise InvalidError(f"argument {decl.name} must be a tensor")
+            if not a.is_contiguous():
+                raise InvalidError(f"argument {decl.name} must be contiguous (flat arrays)")
+            if a.dtype != torch_dtype(decl.dtype):
+                raise MismatchError(f"argument {decl.name}: expected {torch_dtype(decl.dtype)}, "
+                                    f"got {a.dtype}")
+            if n is None:
+                n = a.numel()
+            elif a.numel() != n:
+                # all arrays of one elementwise / map-reduce call share a length
+                raise MismatchError("all array arguments must have the same length")
+    return n if n is not None else 0
+
+
+class ElementwiseKernel:
+    """ElementwiseKernel(arguments, operation, name): run ``operation`` for
+    every index i of the (same-length) array arguments."""
+
+    def __init__(self, arguments, operation, name="kernel"):
+        self.kernel = Kernel(operation, arguments, name)
+
+    def __call__(self, *args, stream=None, config=None):
+        n = _tensor_args(self.kernel, args)
+        elementwise(self.kernel, n, args, stream=stream, config=config)
+
+
+_C_NAMES = {"float32": "float", "float64": "double", "int32": "int", "int64": "int64_t",
+            "uint32": "unsigned"}
+
+
+def _c_type_name(dtype_out):
+    if isinstance(dtype_out, str):
+        return dtype_out
+    name = str(dtype_out).replace("torch.", "").replace("<class 'numpy.", "").rstrip("'>")
+    if name in _C_NAMES:
+        return _C_NAMES[name]
+    import numpy as np
+    return _C_NAMES[np.dtype(dtype_out).name]
+
+
+class ReductionKernel:
+    """ReductionKernel(dtype_out, arguments, map_expr, reduce_expr, neutral):
+    calling it returns a 0-d device tensor holding
+    neutral (+) map(0) (+) ... (+) map(n-1)."""
+
+    def __init__(self, dtype_out, arguments, map_expr, reduce_expr, neutral, name="reduce"):
+        self.map_expr = map_expr
+        self.reduce_expr = reduce_expr
+        self.neutral = str(neutral)
+        self.kernel = Kernel(map_expr, f"{_c_type_name(dtype_out)}: {arguments}", name)
+        prepare_reduce(self.kernel, reduce_expr, self.neutral)
+
+    def __call__(self, *args, stream=None, out=None, config=None):
+        import torch
+        n = _tensor_args(self.kernel, args)
+        device = next((a.device for a in args if isinstance(a, torch.Tensor)), torch.device("cuda"))
+        if out is None:
+            out = torch.empty((), dtype=torch_dtype(self.kernel.result_dtype), device=device)
+        return reduce(self.kernel, self.map_expr, self.reduce_expr, self.neutral, n, args, out,
+                      stream=stream, config=config)

@@ -1,0 +1,144 @@
+"""CPU tests of the C ABI library: it loads, exports every symbol the
+header declares, and its host logic (signature parser, expression
+classifier, code generation, hipRTC compile cache, SHA-256, error codes)
+behaves.  No kernel is launched here."""
+
+import ctypes
+import hashlib
+import os
+import re
+
+import pytest
+
+import paper_1304_5553_amd as hm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hipmr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hipmr_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(hm.hipmr.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert set(declared_functions()) <= set(hm.hipmr._SIGS)
+
+
+@pytest.mark.parametrize("data", [b"", b"abc", b"a" * 55, b"a" * 56, b"a" * 64, b"x" * 1000,
+                                  bytes(range(256)) * 3])
+def test_sha256_matches_hashlib(data):
+    assert hm.sha256_hex(data) == hashlib.sha256(data).hexdigest()
+
+
+def test_classifier_read_write_sets():
+    k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y")
+    assert k.vectorizable and k.vec == 4
+    assert [(a.read, a.written) for a in k.args] == [(0, 1), (1, 0), (1, 0)]
+    k = hm.compile("a[i] *= 2", "float *a")
+    assert [(a.read, a.written) for a in k.args] == [(1, 1)]
+    k = hm.compile("if (x[i] > 0) z[i] = 1; else z[i] = 2", "float *z, const float *x")
+    assert k.vectorizable
+    src = k.source(0)
+    assert "hipmr_load<NT>(hipmr_p_z" in src          # conditional write: z is loaded first
+    k = hm.compile("z[i] = x[i + 1]", "float *z, const float *x")
+    assert not k.vectorizable
+    k = hm.compile("q[i] = x[i]", "fp8_e4m3 *q, const bfloat16 *x")
+    assert k.vec == 16                                 # 16 bytes of the narrowest array
+
+
+def test_generated_source_shape():
+    k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y",
+                   name="lin")
+    src = k.source(0)
+    assert 'extern "C" __global__' in src and "__launch_bounds__(256)" in src
+    assert re.search(r"lin_ew_[0-9a-f]{8}\(", src)
+    assert "hipmr_p_x[hipmr_u].v[hipmr_j]" in src
+    assert "hipmr_load<NT>(hipmr_p_z" not in src       # write-only: never loaded
+    r = hm.compile("x[i]", "float: const float *x", name="mx")
+    s1 = r.source(2, "max(a,b)", "-INFINITY")
+    assert "__builtin_elementwise_maximum(a, b)" in s1 and "hipmr_block_reduce" in s1
+    s2 = r.source(4, "a+b", "0")
+    assert "hipmr_partial[k]" in s2
+    with pytest.raises(hm.MismatchError):
+        r.source(0)
+
+
+@pytest.mark.parametrize("expr,dtypes,exc", [
+    ("z[i] = x[i]", "float *z, const quux *x", hm.ParseError),
+    ("z[i] = x[i]", "float *z, float *z", hm.ParseError),
+    ("z[i] = x[i]", "float *i, const float *x", hm.ParseError),
+    ("z[i] = x[i] +* 2", "float *z, const float *x", hm.CompileError),
+    ("return; z[i] = 1", "float *z", hm.UnsupportedError),
+    ("z[i] = (x[i]", "float *z, const float *x", hm.ParseError),
+    ("x[i] = 1", "float: float *x", hm.UnsupportedError),
+    ("x[i] = 1", "const float *x", hm.ParseError),
+    ("x[i]", "bfloat16: const float *x", hm.UnsupportedError),
+    ("a = 2; z[i] = a", "float *z, float a", hm.UnsupportedError),
+])
+def test_errors_map_to_exceptions(expr, dtypes, exc):
+    with pytest.raises(exc) as e:
+        hm.compile(expr, dtypes)
+    assert str(e.value)
+
+
+def test_compile_error_carries_the_hiprtc_log():
+    with pytest.raises(hm.CompileError) as e:
+        hm.compile("z[i] = undefined_thing(x[i])", "float *z, const float *x")
+    assert "undefined_thing" in str(e.value)
+
+
+def test_compile_cache_memory_and_disk(tmp_path, monkeypatch):
+    # a source the process has not seen: first a compile, then memory hits
+    tag = os.urandom(4).hex()
+    expr = f"z[i] = x[i] * 3.0f + {int(tag, 16) % 1000}"
+    s0 = hm.cache_stats()
+    hm.compile(expr, "float *z, const float *x")
+    s1 = hm.cache_stats()
+    assert s1["compiles"] + s1["disk_hits"] == s0["compiles"] + s0["disk_hits"] + 1
+    hm.compile(expr, "float *z, const float *x")
+    s2 = hm.cache_stats()
+    assert s2["memory_hits"] == s1["memory_hits"] + 1 and s2["compiles"] == s1["compiles"]
+    # after dropping the memory cache the same source loads from disk
+    hm.cache_drop_memory()
+    hm.compile(expr, "float *z, const float *x")
+    s3 = hm.cache_stats()
+    assert s3["disk_hits"] == s2["disk_hits"] + 1 and s3["compiles"] == s2["compiles"]
+
+
+def test_corrupt_disk_entry_is_rebuilt():
+    cache = os.environ.get("HIPMR_CACHE_DIR") or os.path.join(
+        os.environ.get("XDG_CACHE_HOME") or os.path.expanduser("~/.cache"), "hipmr")
+    tag = os.urandom(4).hex()
+    expr = f"z[i] = x[i] - {int(tag, 16) % 100000}"
+    hm.compile(expr, "float *z, const float *x")
+    newest = max((os.path.join(cache, f) for f in os.listdir(cache) if f.endswith(".hsaco")),
+                 key=os.path.getmtime)
+    with open(newest, "r+b") as f:
+        f.seek(200)
+        f.write(b"\x00garbage\x00")
+    hm.cache_drop_memory()
+    s0 = hm.cache_stats()
+    hm.compile(expr, "float *z, const float *x")
+    s1 = hm.cache_stats()
+    assert s1["disk_rejects"] == s0["disk_rejects"] + 1
+    assert s1["compiles"] == s0["compiles"] + 1
+
+
+def test_prepare_reduce_builds_without_a_gpu():
+    k = hm.compile("k[i] % 7 == 3", "long: const int *k")
+    hm.prepare_reduce(k, "a+b", "0")
+    assert hm.reduce_workspace_bytes(k, 1 << 28) >= 8 * 2048
+
+
+def test_selftest_compiles_every_template():
+    assert hm.selftest_compile() >= 30
