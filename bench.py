@@ -40,9 +40,33 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=1 << 28)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=1 << 25,
+    p.add_argument("--cpu-sample", type=int, default=1 << 27,
                    help="elements per op for the oracle timing")
+    p.add_argument("--ops", default="E1,E2,R1,R2,R3",
+                   help="comma list of E1,E2,R1,R2,R3 and COPY (z[i] = x[i], the plain copy "
+                        "kernel used to calibrate the HBM byte counters)")
     return p.parse_args()
+
+
+COUNTERS_MD = "profiles/plain_n2e28_hbm_counters.md"
+
+
+def counter_traffic(symbol):
+    """HBM bytes per launch of `symbol` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on the copy kernel), or None
+    when that exact kernel (its symbol carries a hash of its source) has not
+    been profiled."""
+    path = os.path.join(ROOT, COUNTERS_MD)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 4 and cells[0] == symbol:
+            try:
+                return int(float(cells[3]))
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_baseline(x, y, k, sample):
@@ -100,13 +124,17 @@ def main():
             "R1": hm.compile(workloads.R_COUNT[1], workloads.R_COUNT[0], name="r1_count"),
             "R2": hm.compile(workloads.R_SUM[1], workloads.R_SUM[0], name="r2_sum"),
             "R3": hm.compile(workloads.R_MAX[1], workloads.R_MAX[0], name="r3_max"),
+            "COPY": hm.compile("z[i] = x[i]", "float *z, const float *x", name="copy"),
         }
 
     ks = kernels()
     stream = torch.cuda.current_stream()
     ws = hm.hipmr.workspace(hm.reduce_workspace_bytes(ks["R1"], n), dev, stream.cuda_stream)
-    bytes_per = {"E1": 12 * n, "E2": 12 * n, "R1": 4 * n, "R2": 4 * n, "R3": 4 * n}
-    ops = ["E1", "E2", "R1", "R2", "R3"]
+    bytes_per = {"E1": 12 * n, "E2": 12 * n, "R1": 4 * n, "R2": 4 * n, "R3": 4 * n, "COPY": 8 * n}
+    ops = [o.strip().upper() for o in args.ops.split(",") if o.strip()]
+    if any(o not in bytes_per for o in ops):
+        print(f"bench.py: unknown op in --ops {args.ops}", file=sys.stderr)
+        sys.exit(2)
 
     def run_op(name, kk):
         if name == "E1":
@@ -117,6 +145,8 @@ def main():
             hm.reduce(kk["R1"], workloads.R_COUNT[1], "a+b", "0", n, [kd], outs["count"], ws)
         elif name == "R2":
             hm.reduce(kk["R2"], workloads.R_SUM[1], "a+b", "0", n, [kd], outs["sum"], ws)
+        elif name == "COPY":
+            hm.elementwise(kk["COPY"], n, [z, xd])
         else:
             hm.reduce(kk["R3"], workloads.R_MAX[1], "max(a,b)", "-INFINITY", n, [xd],
                       outs["max"], ws)
@@ -152,7 +182,7 @@ def main():
         per_op_ms[name] = [a.elapsed_time(b) for a, b in ev[name]]
 
     ms_per_step = total_ms / args.steps
-    step_bytes = sum(bytes_per.values())
+    step_bytes = sum(bytes_per[o] for o in ops)
     value = step_bytes / (ms_per_step / 1e3) / 1e9
     op_stats = {}
     for name in ops:
@@ -163,10 +193,17 @@ def main():
     dominant = max(ops, key=lambda o: np.mean(per_op_ms[o]))
     dom_ms = float(np.mean(per_op_ms[dominant]))
     achieved = bytes_per[dominant] / (dom_ms / 1e3) / 1e9
+    dom_symbol = ks[dominant].last_symbols()[0]
+    traffic = counter_traffic(dom_symbol)
 
     # results of the last step (sanity: exact integer results are printed)
-    result = {"R1_count": int(outs["count"].item()), "R2_sum": int(outs["sum"].item()),
-              "R3_max": float(outs["max"].item())}
+    result = {}
+    if "R1" in ops:
+        result["R1_count"] = int(outs["count"].item())
+    if "R2" in ops:
+        result["R2_sum"] = int(outs["sum"].item())
+    if "R3" in ops:
+        result["R3_max"] = float(outs["max"].item())
 
     line = {
         "metric": METRIC,
@@ -184,12 +221,14 @@ def main():
         "config": {"workload": "plain fused elementwise + map-reduce at n=2^28: "
                                "E1 z=2.5x-0.5y, E2 z=sqrt(x*x+y*y), R1 count(k%7==3), "
                                "R2 sum(k), R3 max(x)",
-                   "n": n, "step_bytes": step_bytes},
+                   "n": n, "ops": ops, "step_bytes": step_bytes},
         "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "avg_launch_ms": round(dom_ms, 4), "traffic": None},
+                     "avg_launch_ms": round(dom_ms, 4), "symbol": dom_symbol,
+                     "traffic": traffic,
+                     "traffic_source": COUNTERS_MD if traffic is not None else None},
         "ops": op_stats,
         "results": result,
         "wall_s_timed": round(wall, 3),

@@ -102,9 +102,11 @@ typedef struct hipmr_launch_config {
     int32_t flags;            /* HIPMR_CFG_* bits                                       */
 } hipmr_launch_config;
 
-#define HIPMR_CFG_NONTEMPORAL  1  /* streaming (non-temporal) loads and stores        */
-#define HIPMR_CFG_FORCE_SCALAR 2  /* use the one-element-per-step kernel variant      */
-#define HIPMR_CFG_TEMPORAL     4  /* force ordinary (temporal) loads and stores       */
+#define HIPMR_CFG_NONTEMPORAL      1  /* streaming (non-temporal) loads and stores (default) */
+#define HIPMR_CFG_FORCE_SCALAR     2  /* use the one-element-per-step kernel variant         */
+#define HIPMR_CFG_TEMPORAL         4  /* ordinary (temporal) loads and stores                */
+#define HIPMR_CFG_TEMPORAL_LOADS   8  /* ordinary loads, streaming stores                    */
+#define HIPMR_CFG_TEMPORAL_STORES 16  /* streaming loads, ordinary stores                    */
 
 /* ------------------------------------------------------------------ core */
 
@@ -213,6 +215,11 @@ hipmr_status hipmr_get_arg_info(hipmr_handle h, int32_t k, int32_t *dtype, int32
  * length (without NUL). */
 hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char *combine_op,
                                      const char *neutral, char *buf, size_t cap, size_t *len);
+
+/* Symbols of the kernels the most recent elementwise / reduce call on this
+ * handle launched (in launch order, comma-separated), e.g. for matching
+ * profiler output.  Same buffer convention as hipmr_get_kernel_source. */
+hipmr_status hipmr_get_last_symbols(hipmr_handle h, char *buf, size_t cap, size_t *len);
 
 /* Compile-cache counters (process-wide).  Section "Core Method": a source
  * already compiled is found in memory or in the on-disk cache

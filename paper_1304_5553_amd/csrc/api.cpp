@@ -18,6 +18,7 @@ struct hipmr_kernel {
     int default_vec = 4;
     std::mutex mu;
     std::map<std::string, std::shared_ptr<CodeObject>> variants;
+    std::string last_symbols;   // kernels of the most recent launch sequence
 };
 
 namespace {
@@ -25,8 +26,13 @@ namespace {
 constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
 constexpr int kStage2Block = 256;
 
-// default geometry (overridable per call through hipmr_launch_config)
-constexpr int kEwBlock = 256, kEwIpt = 4, kRedBlock = 256, kRedIpt = 8, kBlocksPerCu = 8;
+// Default geometry (overridable per call through hipmr_launch_config), from
+// sweeps on MI355X at n = 2^28: streaming reads reach their best rate with a
+// small resident grid (2 blocks of 256 threads per CU, 4 chunks of 16 bytes
+// in flight per thread and array); elementwise kernels, which mix reads and
+// writes, do best as one pass over a full grid (one chunk per thread).
+constexpr int kEwBlock = 256, kEwIpt = 1, kEwBlocksPerCu = 1 << 20;
+constexpr int kRedBlock = 256, kRedIpt = 4, kRedBlocksPerCu = 2;
 
 int default_vec_for(const Signature& sig) {
     int min_size = 0;
@@ -41,12 +47,13 @@ int default_vec_for(const Signature& sig) {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
-hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int vec, LaunchCfg* out) {
+hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int vec,
+                         int blocks_per_cu, LaunchCfg* out) {
     *out = LaunchCfg();
     out->block = block;
     out->ipt = ipt;
     out->vec = vec;
-    out->blocks_per_cu = kBlocksPerCu;
+    out->blocks_per_cu = blocks_per_cu;
     if (!c) return HIPMR_OK;
     if (c->block) {
         if (c->block < 64 || c->block > 1024 || c->block % 64)
@@ -67,8 +74,10 @@ hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int v
         return fail(HIPMR_E_INVALID, "launch config: negative grid or blocks_per_cu");
     out->grid = c->grid;
     if (c->blocks_per_cu) out->blocks_per_cu = c->blocks_per_cu;
-    if (c->flags & HIPMR_CFG_TEMPORAL) out->nontemporal = false;
-    if (c->flags & HIPMR_CFG_NONTEMPORAL) out->nontemporal = true;
+    if (c->flags & HIPMR_CFG_TEMPORAL) out->nt_loads = out->nt_stores = false;
+    if (c->flags & HIPMR_CFG_NONTEMPORAL) out->nt_loads = out->nt_stores = true;
+    if (c->flags & HIPMR_CFG_TEMPORAL_LOADS) out->nt_loads = false;
+    if (c->flags & HIPMR_CFG_TEMPORAL_STORES) out->nt_stores = false;
     out->force_scalar = (c->flags & HIPMR_CFG_FORCE_SCALAR) != 0;
     return HIPMR_OK;
 }
@@ -76,7 +85,8 @@ hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int v
 std::string spec_key(const KernelSpec& s) {
     return std::to_string((int)s.kind) + "|" + std::to_string(s.idx64) + "|" +
            std::to_string(s.block) + "|" + std::to_string(s.ipt) + "|" + std::to_string(s.vec) +
-           "|" + std::to_string(s.nontemporal) + "|" + s.combine + "\x1f" + s.neutral;
+           "|" + std::to_string(s.nt_loads) + std::to_string(s.nt_stores) + "|" + s.combine +
+           "\x1f" + s.neutral;
 }
 
 hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out) {
@@ -100,11 +110,19 @@ hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_pt
     return HIPMR_OK;
 }
 
-hipmr_status variant_function(hipmr_kernel* h, const KernelSpec& spec, void** fn) {
+// Function of a variant on the current device; appends its symbol to *syms.
+hipmr_status variant_function(hipmr_kernel* h, const KernelSpec& spec, void** fn,
+                              std::string* syms) {
     std::shared_ptr<CodeObject> co;
     hipmr_status st = get_variant(h, spec, &co);
     if (st != HIPMR_OK) return st;
+    if (syms) *syms += (syms->empty() ? "" : ",") + code_object_symbol(*co);
     return get_function(*co, fn);
+}
+
+void set_last_symbols(hipmr_kernel* h, const std::string& syms) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->last_symbols = syms;
 }
 
 // Element offset "head" at which every accessed array is aligned for the
@@ -140,6 +158,7 @@ hipmr_status check_args(hipmr_kernel* h, int64_t n, void* const* args) {
 }
 
 int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap) {
+    cap = (int)std::min<long long>(cap, ((1LL << 32) - 1) / cfg.block);   // threads < 2^32
     if (cfg.grid > 0) return std::min(cfg.grid, cap);
     long long need = (work_units + per_block - 1) / per_block;
     long long limit = (long long)cfg.blocks_per_cu * device_cu_count();
@@ -196,7 +215,8 @@ KernelSpec s1_spec(const hipmr_kernel* h, bool vector, const LaunchCfg& cfg, boo
     s.block = cfg.block;
     s.ipt = cfg.ipt;
     s.vec = vector ? cfg.vec : 1;
-    s.nontemporal = cfg.nontemporal;
+    s.nt_loads = cfg.nt_loads;
+    s.nt_stores = cfg.nt_stores;
     s.combine = combine;
     s.neutral = neutral;
     return s;
@@ -235,7 +255,7 @@ hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void* const* args,
     if (st != HIPMR_OK) return st;
     if (h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "map-reduce handle passed to hipmr_elementwise");
     LaunchCfg cfg;
-    st = resolve_cfg(cfgp, kEwBlock, kEwIpt, h->default_vec, &cfg);
+    st = resolve_cfg(cfgp, kEwBlock, kEwIpt, h->default_vec, kEwBlocksPerCu, &cfg);
     if (st != HIPMR_OK) return st;
     if (n == 0) return HIPMR_OK;
     long long head = -1;
@@ -248,10 +268,13 @@ hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void* const* args,
     spec.block = cfg.block;
     spec.ipt = cfg.ipt;
     spec.vec = vector ? cfg.vec : 1;
-    spec.nontemporal = cfg.nontemporal;
+    spec.nt_loads = cfg.nt_loads;
+    spec.nt_stores = cfg.nt_stores;
     void* fn = nullptr;
-    st = variant_function(h, spec, &fn);
+    std::string syms;
+    st = variant_function(h, spec, &fn, &syms);
     if (st != HIPMR_OK) return st;
+    set_last_symbols(h, syms);
     long long n64 = n, head64 = vector ? head : 0;
     long long units = vector ? (n64 > head64 ? (n64 - head64) / cfg.vec : 0) : n64;
     int grid = grid_for(units, cfg.block * (vector ? cfg.ipt : 1), cfg, 1 << 30);
@@ -278,7 +301,7 @@ hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char* combine, const cha
     if (!h || !combine || !neutral) return fail(HIPMR_E_INVALID, "NULL argument");
     if (!h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "elementwise handle");
     LaunchCfg cfg;
-    resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, &cfg);
+    resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
     std::shared_ptr<CodeObject> co;
     hipmr_status st = get_variant(h, s1_spec(h, h->prog.info.vectorizable, cfg, false, combine, neutral), &co);
     if (st != HIPMR_OK) return st;
@@ -300,11 +323,12 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* c
     if (!workspace || workspace_bytes < hipmr_reduce_workspace_bytes(h, n))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_reduce_workspace_bytes()");
     LaunchCfg cfg;
-    st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, &cfg);
+    st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
     if (st != HIPMR_OK) return st;
 
     long long n64 = n, head64 = 0;
     int grid = 0;
+    std::string syms;
     if (n > 0) {
         long long head = -1;
         bool vector = h->prog.info.vectorizable && !cfg.force_scalar;
@@ -312,7 +336,8 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* c
         if (head < 0) vector = false;
         head64 = vector ? head : 0;
         void* fn = nullptr;
-        st = variant_function(h, s1_spec(h, vector, cfg, n >= (int64_t(1) << 31), combine, neutral), &fn);
+        st = variant_function(h, s1_spec(h, vector, cfg, n >= (int64_t(1) << 31), combine, neutral), &fn,
+                              &syms);
         if (st != HIPMR_OK) return st;
         long long units = vector ? (n64 > head64 ? (n64 - head64) / cfg.vec : 0) : n64;
         grid = grid_for(units, cfg.block * (vector ? cfg.ipt : 1), cfg, kMaxPartials);
@@ -326,8 +351,9 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* c
         if (st != HIPMR_OK) return st;
     }
     void* fn2 = nullptr;
-    st = variant_function(h, s2_spec(combine, neutral), &fn2);
+    st = variant_function(h, s2_spec(combine, neutral), &fn2, &syms);
     if (st != HIPMR_OK) return st;
+    set_last_symbols(h, syms);
     void* params2[3] = {&workspace, &grid, &out};
     return launch(fn2, 1, kStage2Block, params2, stream);
 }
@@ -382,7 +408,8 @@ hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char* c
     if (red != (bool)h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "kind does not match the handle");
     if (red && (!combine || !neutral)) return fail(HIPMR_E_INVALID, "combine_op and neutral are required");
     LaunchCfg cfg;
-    resolve_cfg(nullptr, red ? kRedBlock : kEwBlock, red ? kRedIpt : kEwIpt, h->default_vec, &cfg);
+    resolve_cfg(nullptr, red ? kRedBlock : kEwBlock, red ? kRedIpt : kEwIpt, h->default_vec,
+                red ? kRedBlocksPerCu : kEwBlocksPerCu, &cfg);
     KernelSpec spec;
     if (kind == 4) {
         spec = s2_spec(combine, neutral);
@@ -400,6 +427,23 @@ hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char* c
     if (buf && cap) {
         size_t c = std::min(cap - 1, src.size());
         std::memcpy(buf, src.data(), c);
+        buf[c] = '\0';
+    }
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_get_last_symbols(hipmr_handle h, char* buf, size_t cap, size_t* len) {
+    clear_error();
+    if (!h) return fail(HIPMR_E_INVALID, "NULL handle");
+    std::string syms;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        syms = h->last_symbols;
+    }
+    if (len) *len = syms.size();
+    if (buf && cap) {
+        size_t c = std::min(cap - 1, syms.size());
+        std::memcpy(buf, syms.data(), c);
         buf[c] = '\0';
     }
     return HIPMR_OK;
@@ -447,7 +491,7 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         std::shared_ptr<CodeObject> co;
         if (h->prog.sig.is_reduce) {
             LaunchCfg cfg;
-            resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, &cfg);
+            resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
             for (bool vector : {true, false}) {
                 if (vector && !h->prog.info.vectorizable) continue;
                 for (bool idx64 : {false, true}) {

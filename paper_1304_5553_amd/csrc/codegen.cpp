@@ -208,7 +208,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 {
   typedef @@IDX@@ hipmr_idx;
   constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
-  constexpr bool NT = @@NT@@;
+  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
   // elements [0, head) precede the first aligned chunk; [t0, n) is the ragged tail
   const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
@@ -294,7 +294,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 {
   typedef @@IDX@@ hipmr_idx;
   constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
-  constexpr bool NT = @@NT@@;
+  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   hipmr_acc hipmr_a[U];
@@ -450,9 +450,9 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
         decl_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", V> hipmr_p_" +
                       a.name + "[U]; ";
         if (!a.write_only)
-            loads += "hipmr_load<NT>(hipmr_p_" + a.name + "[hipmr_u], " + a.name + " + hipmr_off); ";
+            loads += "hipmr_load<NTL>(hipmr_p_" + a.name + "[hipmr_u], " + a.name + " + hipmr_off); ";
         if (a.written)
-            stores += "hipmr_store<NT>(" + a.name + " + hipmr_off, hipmr_p_" + a.name + "[hipmr_u]); ";
+            stores += "hipmr_store<NTS>(" + a.name + " + hipmr_off, hipmr_p_" + a.name + "[hipmr_u]); ";
     }
 
     std::string scalar_text = join_tokens(prog.toks);
@@ -471,7 +471,8 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     replace_all(body, "@@BLOCK@@", std::to_string(spec.block));
     replace_all(body, "@@IPT@@", std::to_string(spec.ipt));
     replace_all(body, "@@VEC@@", std::to_string(spec.vec));
-    replace_all(body, "@@NT@@", spec.nontemporal ? "true" : "false");
+    replace_all(body, "@@NTL@@", spec.nt_loads ? "true" : "false");
+    replace_all(body, "@@NTS@@", spec.nt_stores ? "true" : "false");
 
     std::ostringstream src;
     src << "// generated by hipmr: " << tag << " kernel of \"" << prog.name << "\"\n";

@@ -90,7 +90,8 @@ struct LaunchCfg {
     int grid = 0;         // 0: derived
     int blocks_per_cu = 8;
     int vec = 0;          // 0: derived
-    bool nontemporal = true;
+    bool nt_loads = true;   // streaming (non-temporal) loads
+    bool nt_stores = true;  // streaming (non-temporal) stores
     bool force_scalar = false;
 };
 
@@ -105,7 +106,8 @@ struct KernelSpec {
     int block = 256;
     int ipt = 4;
     int vec = 4;
-    bool nontemporal = true;
+    bool nt_loads = true;
+    bool nt_stores = true;
     std::string combine;      // reduce kinds
     std::string neutral;
 };
@@ -128,6 +130,8 @@ struct CodeObject;   // opaque: compiled image + per-device modules/functions
 // the GPU.  Returns nullptr with last_error set on failure.
 std::shared_ptr<CodeObject> get_or_build(const std::string& source, const std::string& symbol,
                                          hipmr_status* status);
+
+const std::string& code_object_symbol(const CodeObject& co);
 
 // hipFunction_t (as void*) of the code object on the current device; loads the
 // module on first use on that device.

@@ -241,6 +241,8 @@ hipmr_status launch(void* fn, unsigned grid, unsigned block, void** params, void
     return HIPMR_OK;
 }
 
+const std::string& code_object_symbol(const CodeObject& co) { return co.symbol; }
+
 void cache_stats(hipmr_cache_stats* out) {
     out->memory_hits = g_mem_hits.load();
     out->disk_hits = g_disk_hits.load();

@@ -31,6 +31,7 @@ DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "i
                BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3"}
 
 CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
+CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES = 8, 16
 
 
 class HipmrError(RuntimeError):
@@ -116,6 +117,7 @@ _SIGS = {
     "hipmr_get_handle_info": (_I32, [_VP, ctypes.POINTER(HandleInfo)]),
     "hipmr_get_arg_info": (_I32, [_VP, _I32] + [ctypes.POINTER(_I32)] * 5),
     "hipmr_get_kernel_source": (_I32, [_VP, _I32, _CP, _CP, _CP, _SZ, ctypes.POINTER(_SZ)]),
+    "hipmr_get_last_symbols": (_I32, [_VP, _CP, _SZ, ctypes.POINTER(_SZ)]),
     "hipmr_get_cache_stats": (_I32, [ctypes.POINTER(CacheStats)]),
     "hipmr_cache_drop_memory": (None, []),
     "hipmr_sha256_hex": (_I32, [_VP, _SZ, _CP]),
@@ -253,6 +255,13 @@ class Kernel:
             keep.append(c)
             ptrs[k] = ctypes.cast(ctypes.byref(c), ctypes.c_void_p)
         return keep, ptrs
+
+    def last_symbols(self):
+        """Symbols of the kernels the last call on this handle launched."""
+        buf = ctypes.create_string_buffer(4096)
+        ln = ctypes.c_size_t()
+        _check(lib().hipmr_get_last_symbols(self._h, buf, len(buf), ctypes.byref(ln)))
+        return [s for s in buf.value.decode().split(",") if s]
 
     def source(self, kind, combine_op=None, neutral=None):
         ln = ctypes.c_size_t()
