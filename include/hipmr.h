@@ -144,9 +144,9 @@ hipmr_status hipmr_elementwise(hipmr_handle h, int64_t n, void *const *args, voi
 hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void *const *args,
                                   const hipmr_launch_config *cfg, void *stream);
 
-/* Bytes of device workspace hipmr_reduce needs for n elements (depends only
- * on the handle's result type and the device's CU count; a few tens of KiB).
- * Returns 0 for an invalid handle. */
+/* Bytes of device workspace hipmr_reduce, hipmr_reduce_compensated and
+ * hipmr_norm2 need (64 KiB of block partials plus 256 bytes for the norm's
+ * scale; independent of n).  Returns 0 for an elementwise or invalid handle. */
 size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n);
 
 /* Map-reduce: *out = neutral (+) map(0) (+) ... (+) map(n-1), (+) being
@@ -188,6 +188,45 @@ const char *hipmr_last_error(void);
 /* Drops one reference; the handle must not be used afterwards.  Cached code
  * objects stay in the process-wide cache. NULL is ignored. */
 void hipmr_release(hipmr_handle h);
+
+/* ------------------------------------------------------------------ precision extension */
+
+/* Compensated sum of a float map: *out (double) = post_scale * sum_i map(i).
+ * Precision extension of the map-reduce (section "Map-Reduce"): the map is
+ * evaluated in float from narrow loads (bfloat16, half, fp8_e4m3 or float
+ * arrays), accumulated per lane with Kahan compensation in FP32, combined
+ * across lanes, waves and the block as (sum, error) pairs with error-free
+ * TwoSum steps, written as FP64 block partials and folded in FP64 (Neumaier)
+ * by one block, which multiplies by post_scale once (for example 1/s of a
+ * per-tensor power-of-two quantisation scale s).  When the map is a single
+ * FP8 load, runs of up to 64 values are summed in plain FP32, which is exact
+ * (every E4M3 value is a multiple of 2^-9 of magnitude at most 448), and
+ * compensated once per run.
+ *   h:         map-reduce handle with result type float ("float: ...").
+ *   out:       device pointer to one double.
+ *   workspace: at least hipmr_reduce_workspace_bytes(h, n) bytes.
+ *   cfg:       NULL or a launch geometry.
+ * n == 0 writes 0.  Errors: as hipmr_reduce; E_MISMATCH for a handle whose
+ * result type is not float. */
+hipmr_status hipmr_reduce_compensated(hipmr_handle h, int64_t n, void *const *args,
+                                      double post_scale, void *out, void *workspace,
+                                      size_t workspace_bytes, const hipmr_launch_config *cfg,
+                                      void *stream);
+
+/* L2 norm of a float map: *out (double) = post_scale * sqrt(sum_i map(i)^2),
+ * precision extension as above.
+ *   passes == 2 (scaled): pass 1 takes the exact max |map(i)| and derives, on
+ *     the device, the power of two s that puts it in [1, 2) (exponent clamped
+ *     to [-126, 126]); pass 2 accumulates (map(i) * s)^2 with compensation and
+ *     the final FP64 step returns post_scale * sqrt(sum) / s.  Reads the data
+ *     twice.
+ *   passes == 1: no scaling, one read; the squares must stay inside the float
+ *     range (true for every half or FP8 load: their squares are below 2^32).
+ * The scale is kept in the workspace between the two passes.  Errors: as
+ * hipmr_reduce_compensated; E_INVALID for passes other than 1 or 2. */
+hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void *const *args, double post_scale,
+                         int32_t passes, void *out, void *workspace, size_t workspace_bytes,
+                         const hipmr_launch_config *cfg, void *stream);
 
 /* ------------------------------------------------------------------ introspection */
 

@@ -12,9 +12,11 @@ from .hipmr import (CFG_FORCE_SCALAR, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError
                     ElementwiseKernel, HipError, HipmrError, InvalidError, Kernel, LaunchConfig,
                     MismatchError, ParseError, ReductionKernel, UnsupportedError, WorkspaceError,
                     cache_drop_memory, cache_stats, compile, elementwise, lib, prepare_reduce,
-                    reduce, reduce_workspace_bytes, selftest_compile, sha256_hex, torch_dtype)
+                    reduce, reduce_compensated, norm2, reduce_workspace_bytes, selftest_compile,
+                    sha256_hex, torch_dtype)
 
 __all__ = ["ElementwiseKernel", "ReductionKernel", "Kernel", "compile", "elementwise", "reduce",
+           "reduce_compensated", "norm2",
            "prepare_reduce", "reduce_workspace_bytes", "cache_stats", "cache_drop_memory",
            "sha256_hex", "selftest_compile", "lib", "torch_dtype", "LaunchConfig",
            "CFG_NONTEMPORAL", "CFG_TEMPORAL", "CFG_FORCE_SCALAR", "HipmrError", "InvalidError",

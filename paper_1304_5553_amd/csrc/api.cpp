@@ -25,6 +25,10 @@ namespace {
 
 constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
 constexpr int kStage2Block = 256;
+// workspace layout: [0, 64 KiB) block partials; then the norm's scale as a
+// float (+0) and a double (+8)
+constexpr size_t kScaleOffset = (size_t)kMaxPartials * 8;
+constexpr size_t kWorkspaceBytes = kScaleOffset + 256;
 
 // Default geometry (overridable per call through hipmr_launch_config), from
 // sweeps on MI355X at n = 2^28: streaming reads reach their best rate with a
@@ -85,8 +89,9 @@ hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int v
 std::string spec_key(const KernelSpec& s) {
     return std::to_string((int)s.kind) + "|" + std::to_string(s.idx64) + "|" +
            std::to_string(s.block) + "|" + std::to_string(s.ipt) + "|" + std::to_string(s.vec) +
-           "|" + std::to_string(s.nt_loads) + std::to_string(s.nt_stores) + "|" + s.combine +
-           "\x1f" + s.neutral;
+           "|" + std::to_string(s.nt_loads) + std::to_string(s.nt_stores) + "|" +
+           std::to_string(s.square) + std::to_string(s.scaled) + std::to_string(s.exact_runs) +
+           std::to_string(s.norm) + "|" + s.combine + "\x1f" + s.neutral;
 }
 
 hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out) {
@@ -235,6 +240,169 @@ KernelSpec s2_spec(const char* combine, const char* neutral) {
 
 }  // namespace
 
+
+namespace {
+
+// Shared launch logic of the precision extension: one stage-1 kernel over the
+// map (vector when possible), its partials, and one finishing kernel.
+struct Stage1 {
+    void* fn = nullptr;
+    int grid = 0;
+    long long head = 0;
+};
+
+hipmr_status stage1_launch(hipmr_kernel* h, KernelSpec spec, bool vector_ok, const LaunchCfg& cfg,
+                           int64_t n, void* const* args, void* partial, void* extra,
+                           bool with_extra, void* stream, std::string* syms, Stage1* out) {
+    long long head = -1;
+    bool vector = vector_ok && h->prog.info.vectorizable && !cfg.force_scalar;
+    if (vector) head = common_head(h, args, cfg.vec);
+    if (head < 0) vector = false;
+    if (!vector) {
+        switch (spec.kind) {
+            case KernelKind::CompS1Vector: spec.kind = KernelKind::CompS1Scalar; break;
+            case KernelKind::AmaxS1Vector: spec.kind = KernelKind::AmaxS1Scalar; break;
+            default: break;
+        }
+        spec.vec = 1;
+        spec.exact_runs = false;
+    }
+    spec.idx64 = n >= (int64_t(1) << 31);
+    hipmr_status st = variant_function(h, spec, &out->fn, syms);
+    if (st != HIPMR_OK) return st;
+    long long n64 = n, head64 = vector ? head : 0;
+    long long units = vector ? (n64 > head64 ? (n64 - head64) / cfg.vec : 0) : n64;
+    out->grid = n > 0 ? grid_for(units, cfg.block * (vector ? cfg.ipt : 1), cfg, kMaxPartials) : 0;
+    out->head = head64;
+    if (n == 0) return HIPMR_OK;
+    std::vector<void*> params;
+    if (h->prog.sig.args.empty()) params.push_back(&head64);   // hipmr_unused
+    for (size_t k = 0; k < h->prog.sig.args.size(); ++k) params.push_back(args[k]);
+    params.push_back(&n64);
+    params.push_back(&head64);
+    params.push_back(&partial);
+    if (with_extra) params.push_back(&extra);
+    return launch(out->fn, (unsigned)out->grid, (unsigned)cfg.block, params.data(), stream);
+}
+
+KernelSpec comp_spec(KernelKind kind, const LaunchCfg& cfg) {
+    KernelSpec s;
+    s.kind = kind;
+    s.block = cfg.block;
+    s.ipt = cfg.ipt;
+    s.vec = cfg.vec;
+    s.nt_loads = cfg.nt_loads;
+    s.nt_stores = cfg.nt_stores;
+    return s;
+}
+
+// The map is a single load of an FP8 array: runs of <= 64 values sum exactly.
+bool single_fp8_load(const hipmr_kernel* h) {
+    const auto& t = h->prog.toks;
+    if (t.size() != 5 || t[0].kind != Token::Ident || t[1].text != "[" || t[2].text != "i" ||
+        t[3].text != "]")
+        return false;
+    for (const ArgDecl& a : h->prog.sig.args)
+        if (a.name == t[0].text) return a.pointer && a.dtype == DT_FP8;
+    return false;
+}
+
+hipmr_status precision_checks(hipmr_kernel* h, int64_t n, void* const* args, void* out,
+                              void* workspace, size_t workspace_bytes) {
+    hipmr_status st = check_args(h, n, args);
+    if (st != HIPMR_OK) return st;
+    if (!h->prog.sig.is_reduce || h->prog.sig.result != DT_F32)
+        return fail(HIPMR_E_MISMATCH, "the precision extension needs a 'float:' map-reduce handle "
+                                      "(the map is accumulated in compensated float)");
+    if (!out) return fail(HIPMR_E_INVALID, "out is NULL");
+    if (!workspace || workspace_bytes < kWorkspaceBytes)
+        return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_reduce_workspace_bytes()");
+    return HIPMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hipmr_status hipmr_reduce_compensated(hipmr_handle h, int64_t n, void* const* args,
+                                      double post_scale, void* out, void* workspace,
+                                      size_t workspace_bytes, const hipmr_launch_config* cfgp,
+                                      void* stream) {
+    clear_error();
+    hipmr_status st = precision_checks(h, n, args, out, workspace, workspace_bytes);
+    if (st != HIPMR_OK) return st;
+    LaunchCfg cfg;
+    st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
+    if (st != HIPMR_OK) return st;
+    KernelSpec s1 = comp_spec(KernelKind::CompS1Vector, cfg);
+    s1.exact_runs = single_fp8_load(h) && cfg.vec * cfg.ipt <= 64;
+    std::string syms;
+    Stage1 r;
+    st = stage1_launch(h, s1, true, cfg, n, args, workspace, nullptr, true, stream, &syms, &r);
+    if (st != HIPMR_OK) return st;
+    KernelSpec s2 = comp_spec(KernelKind::CompS2, cfg);
+    s2.block = kStage2Block;
+    s2.ipt = s2.vec = 1;
+    void* fn2 = nullptr;
+    st = variant_function(h, s2, &fn2, &syms);
+    if (st != HIPMR_OK) return st;
+    set_last_symbols(h, syms);
+    void* scale64 = (char*)workspace + kScaleOffset + 8;
+    void* params2[5] = {&workspace, &r.grid, &post_scale, &scale64, &out};
+    return launch(fn2, 1, kStage2Block, params2, stream);
+}
+
+hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void* const* args, double post_scale,
+                         int32_t passes, void* out, void* workspace, size_t workspace_bytes,
+                         const hipmr_launch_config* cfgp, void* stream) {
+    clear_error();
+    hipmr_status st = precision_checks(h, n, args, out, workspace, workspace_bytes);
+    if (st != HIPMR_OK) return st;
+    if (passes != 1 && passes != 2) return fail(HIPMR_E_INVALID, "passes must be 1 or 2");
+    LaunchCfg cfg;
+    st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
+    if (st != HIPMR_OK) return st;
+    void* scale_f = (char*)workspace + kScaleOffset;
+    void* scale_d = (char*)workspace + kScaleOffset + 8;
+    std::string syms;
+    if (passes == 2) {
+        // pass 1: exact max |map| -> power-of-two scale, written on the device
+        KernelSpec a1 = comp_spec(KernelKind::AmaxS1Vector, cfg);
+        Stage1 r1;
+        st = stage1_launch(h, a1, true, cfg, n, args, workspace, nullptr, false, stream, &syms, &r1);
+        if (st != HIPMR_OK) return st;
+        KernelSpec a2 = comp_spec(KernelKind::AmaxScale, cfg);
+        a2.block = kStage2Block;
+        a2.ipt = a2.vec = 1;
+        void* fna = nullptr;
+        st = variant_function(h, a2, &fna, &syms);
+        if (st != HIPMR_OK) return st;
+        void* pa[4] = {&workspace, &r1.grid, &scale_f, &scale_d};
+        st = launch(fna, 1, kStage2Block, pa, stream);
+        if (st != HIPMR_OK) return st;
+    }
+    // pass 2 (or the only pass): compensated sum of (map * scale)^2
+    KernelSpec q1 = comp_spec(KernelKind::CompS1Vector, cfg);
+    q1.square = true;
+    q1.scaled = passes == 2;
+    Stage1 r2;
+    st = stage1_launch(h, q1, true, cfg, n, args, workspace, scale_f, true, stream, &syms, &r2);
+    if (st != HIPMR_OK) return st;
+    KernelSpec q2 = comp_spec(KernelKind::CompS2, cfg);
+    q2.block = kStage2Block;
+    q2.ipt = q2.vec = 1;
+    q2.norm = true;
+    q2.scaled = passes == 2;
+    void* fn2 = nullptr;
+    st = variant_function(h, q2, &fn2, &syms);
+    if (st != HIPMR_OK) return st;
+    set_last_symbols(h, syms);
+    void* params2[5] = {&workspace, &r2.grid, &post_scale, &scale_d, &out};
+    return launch(fn2, 1, kStage2Block, params2, stream);
+}
+
+}  // extern "C"
+
 extern "C" {
 
 hipmr_status hipmr_compile(const char* expr, const char* dtypes, hipmr_handle* out) {
@@ -293,7 +461,7 @@ hipmr_status hipmr_elementwise(hipmr_handle h, int64_t n, void* const* args, voi
 size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n) {
     (void)n;
     if (!h || !h->prog.sig.is_reduce) return 0;
-    return (size_t)kMaxPartials * 8;
+    return kWorkspaceBytes;
 }
 
 hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char* combine, const char* neutral) {
@@ -482,6 +650,9 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         {"x[i]", "double: const fp8_e4m3 *x", "min", "INFINITY"},
         {"k[i]", "unsigned: const unsigned *k", "a|b", "0u"},
         {"x[n - 1 - i]", "float: const float *x", "a+b", "0"},
+        {"x[i]", "float: const fp8_e4m3 *x", "a+b", "0"},
+        {"x[i]", "float: const bfloat16 *x", "a+b", "0"},
+        {"x[i] * y[i]", "float: const half *x, const half *y", "a+b", "0"},
     };
     int32_t built = 0;
     for (const Case& c : cases) {
@@ -502,6 +673,41 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
             }
             st = get_variant(h, s2_spec(c.combine, c.neutral), &co);
             ++built;
+            if (st == HIPMR_OK && h->prog.sig.result == DT_F32) {
+                // precision extension: compensated sum, norm passes, finishers
+                std::vector<KernelSpec> specs;
+                for (KernelKind k : {KernelKind::CompS1Vector, KernelKind::CompS1Scalar}) {
+                    for (int variant = 0; variant < 3; ++variant) {
+                        KernelSpec q = comp_spec(k, cfg);
+                        if (k == KernelKind::CompS1Scalar) q.vec = 1;
+                        q.square = variant > 0;
+                        q.scaled = variant == 2;
+                        q.exact_runs = variant == 0 && k == KernelKind::CompS1Vector &&
+                                       single_fp8_load(h);
+                        specs.push_back(q);
+                    }
+                }
+                for (int variant = 0; variant < 3; ++variant) {
+                    KernelSpec q = comp_spec(KernelKind::CompS2, cfg);
+                    q.block = kStage2Block;
+                    q.ipt = q.vec = 1;
+                    q.norm = variant > 0;
+                    q.scaled = variant == 2;
+                    specs.push_back(q);
+                }
+                specs.push_back(comp_spec(KernelKind::AmaxS1Vector, cfg));
+                KernelSpec sc = comp_spec(KernelKind::AmaxScale, cfg);
+                sc.block = kStage2Block;
+                specs.push_back(sc);
+                for (const KernelSpec& q : specs) {
+                    if (!h->prog.info.vectorizable &&
+                        (q.kind == KernelKind::CompS1Vector || q.kind == KernelKind::AmaxS1Vector))
+                        continue;
+                    st = get_variant(h, q, &co);
+                    if (st != HIPMR_OK) break;
+                    ++built;
+                }
+            }
         } else {
             KernelSpec spec;
             spec.kind = KernelKind::EwScalar;

@@ -148,6 +148,30 @@ __device__ __forceinline__ void hipmr_load(hipmr_pack<T, N>& p, const T* src) {
   __builtin_memcpy(&p, tmp, B);
 }
 
+// A read-only chunk of N FP8 values kept as 32-bit words: element j decodes
+// with the byte-select form of the conversion instruction (one instruction
+// per element, no byte extraction).
+template <int N> struct hipmr_fp8_words {
+  unsigned int w[N / 4];
+  __device__ __forceinline__ float operator[](int j) const {
+    const int word = (int)w[j >> 2];
+    switch (j & 3) {
+      case 0: return __builtin_amdgcn_cvt_f32_fp8(word, 0);
+      case 1: return __builtin_amdgcn_cvt_f32_fp8(word, 1);
+      case 2: return __builtin_amdgcn_cvt_f32_fp8(word, 2);
+      default: return __builtin_amdgcn_cvt_f32_fp8(word, 3);
+    }
+  }
+};
+template <int N> struct hipmr_pack_fp8ro { hipmr_fp8_words<N> v; };
+
+template <bool NT, int N>
+__device__ __forceinline__ void hipmr_load(hipmr_pack_fp8ro<N>& p, const hipmr_fp8* src) {
+  hipmr_pack<hipmr_fp8, N> raw;
+  hipmr_load<NT>(raw, src);
+  __builtin_memcpy(&p, &raw, N);
+}
+
 template <bool NT, typename T, int N>
 __device__ __forceinline__ void hipmr_store(T* dst, const hipmr_pack<T, N>& p) {
   constexpr int B = (int)sizeof(T) * N;
@@ -396,6 +420,274 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
+
+// Compensated FP32 accumulation (precision extension).  Error-free
+// transformations must not be contracted into FMAs.
+const char* kCompHelpers = R"HIP(
+#pragma clang fp contract(off)
+// (hi, lo): an unevaluated sum of two floats
+struct hipmr_ff { float hi, lo; };
+struct hipmr_dd { double hi, lo; };
+
+// Kahan: s + (-c) carries the running sum; c holds the rounding lost so far.
+// Once the sum is infinite (or NaN) the correction is dropped, so that an
+// infinity is not turned into a NaN by inf - inf.
+__device__ __forceinline__ void hipmr_kahan_add(float& s, float& c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = __builtin_isfinite(t) ? (t - s) - y : 0.0f;
+  s = t;
+}
+
+// Knuth's TwoSum: a + b = s + e exactly, no ordering assumption
+__device__ __forceinline__ hipmr_ff hipmr_two_sum(float a, float b) {
+  const float s = a + b;
+  const float bb = s - a;
+  return {s, __builtin_isfinite(s) ? (a - (s - bb)) + (b - bb) : 0.0f};
+}
+__device__ __forceinline__ hipmr_ff hipmr_ff_add(hipmr_ff x, hipmr_ff y) {
+  const hipmr_ff s = hipmr_two_sum(x.hi, y.hi);
+  return hipmr_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+__device__ __forceinline__ hipmr_dd hipmr_two_sum_d(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  return {s, __builtin_isfinite(s) ? (a - (s - bb)) + (b - bb) : 0.0};
+}
+__device__ __forceinline__ hipmr_dd hipmr_dd_add(hipmr_dd x, hipmr_dd y) {
+  const hipmr_dd s = hipmr_two_sum_d(x.hi, y.hi);
+  return hipmr_two_sum_d(s.hi, s.lo + (x.lo + y.lo));
+}
+
+// pairwise sum of one chunk's V terms (fixed tree); the chunk sum then
+// enters the compensated accumulator
+template <int V>
+__device__ __forceinline__ float hipmr_chunk_sum(float* t) {
+#pragma unroll
+  for (int w = 1; w < V; w *= 2) {
+#pragma unroll
+    for (int j = 0; j + w < V; j += 2 * w) t[j] += t[j + w];
+  }
+  return t[0];
+}
+
+template <bool SQ>
+__device__ __forceinline__ float hipmr_term(float v, float scale) {
+  if constexpr (SQ) {
+    const float w = v * scale;
+    return w * w;
+  } else {
+    return v;
+  }
+}
+
+// pairwise combination of (hi, lo) pairs across the wave, then the block
+template <int B, typename P, typename F>
+__device__ __forceinline__ P hipmr_block_reduce_pair(P v, F add) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    P o;
+    o.hi = __shfl_xor(v.hi, m, 64);
+    o.lo = __shfl_xor(v.lo, m, 64);
+    v = add(v, o);
+  }
+  if constexpr (B > 64) {
+    constexpr int W = B / 64;
+    constexpr int PW = W <= 2 ? 2 : W <= 4 ? 4 : W <= 8 ? 8 : 16;
+    __shared__ P hipmr_lds_pair[W];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) hipmr_lds_pair[w] = v;
+    __syncthreads();
+    if (w == 0) {
+      if (l < W) v = hipmr_lds_pair[l];
+      else { v.hi = 0; v.lo = 0; }
+#pragma unroll
+      for (int m = PW / 2; m >= 1; m >>= 1) {
+        P o;
+        o.hi = __shfl_xor(v.hi, m, 64);
+        o.lo = __shfl_xor(v.lo, m, 64);
+        v = add(v, o);
+      }
+    }
+  }
+  return v;
+}
+)HIP";
+
+// Stage 1 of a compensated sum (or of the norm's sum of squares).
+const char* kCompS1Vector = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head,
+          double* __restrict__ hipmr_partial, const float* __restrict__ hipmr_scale_p)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
+  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
+  constexpr bool SQ = @@SQUARE@@, RUNS = @@RUNS@@, SCALED = @@SCALED@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  const float hipmr_sc = SCALED ? *hipmr_scale_p : 1.0f;
+  float hipmr_s[U], hipmr_e[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) { hipmr_s[u] = 0.0f; hipmr_e[u] = 0.0f; }
+  const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * V;
+  if (blockIdx.x == 0) {
+    if ((long long)threadIdx.x < hipmr_h) {
+      const hipmr_idx i = (hipmr_idx)threadIdx.x;
+      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+    }
+    if ((long long)threadIdx.x < hipmr_n - hipmr_t0) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_t0 + threadIdx.x);
+      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+    }
+  }
+  const long long hipmr_step = (long long)gridDim.x * (B * U);
+  long long hipmr_c0 = (long long)blockIdx.x * (B * U) + threadIdx.x;
+  for (; hipmr_c0 + (U - 1) * B < hipmr_nc; hipmr_c0 += hipmr_step) {
+    @@DECL_PACKS@@
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+      @@LOADS@@
+    }
+    if constexpr (RUNS) {
+      // every value is k * 2^-9 with |k| <= 229376: a float sum of at most
+      // 64 of them is exact, so one compensated step per run suffices
+      float hipmr_run = 0.0f;
+#pragma unroll
+      for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_run += (float)(@@VMAP@@);
+        }
+      }
+      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_run);
+    } else {
+#pragma unroll
+      for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+        float hipmr_t[V];
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_t[hipmr_j] = hipmr_term<SQ>((float)(@@VMAP@@), hipmr_sc);
+        }
+        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<V>(hipmr_t));
+      }
+    }
+  }
+  if (hipmr_c0 < hipmr_nc) {
+    @@DECL_PACKS@@
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+      if (hipmr_c < hipmr_nc) {
+        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        @@LOADS@@
+      }
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+      if (hipmr_c < hipmr_nc) {
+        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        float hipmr_t[V];
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_t[hipmr_j] = hipmr_term<SQ>((float)(@@VMAP@@), hipmr_sc);
+        }
+        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<V>(hipmr_t));
+      }
+    }
+  }
+  hipmr_ff hipmr_r = {hipmr_s[0], -hipmr_e[0]};
+#pragma unroll
+  for (int u = 1; u < U; ++u) hipmr_r = hipmr_ff_add(hipmr_r, hipmr_ff{hipmr_s[u], -hipmr_e[u]});
+  hipmr_r = hipmr_block_reduce_pair<B>(hipmr_r, [](hipmr_ff a, hipmr_ff b) { return hipmr_ff_add(a, b); });
+  if (threadIdx.x == 0)
+    hipmr_partial[blockIdx.x] = __builtin_isfinite(hipmr_r.hi) ? (double)hipmr_r.hi + (double)hipmr_r.lo
+                                                               : (double)hipmr_r.hi;
+}
+)HIP";
+
+const char* kCompS1Scalar = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head,
+          double* __restrict__ hipmr_partial, const float* __restrict__ hipmr_scale_p)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr bool SQ = @@SQUARE@@, SCALED = @@SCALED@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  const float hipmr_sc = SCALED ? *hipmr_scale_p : 1.0f;
+  float hipmr_s = 0.0f, hipmr_cc = 0.0f;
+  const long long hipmr_step = (long long)gridDim.x * @@BLOCK@@;
+  for (long long hipmr_k = (long long)blockIdx.x * @@BLOCK@@ + threadIdx.x; hipmr_k < hipmr_n;
+       hipmr_k += hipmr_step) {
+    const hipmr_idx i = (hipmr_idx)hipmr_k;
+    hipmr_kahan_add(hipmr_s, hipmr_cc, hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+  }
+  hipmr_ff hipmr_r = {hipmr_s, -hipmr_cc};
+  hipmr_r = hipmr_block_reduce_pair<@@BLOCK@@>(hipmr_r, [](hipmr_ff a, hipmr_ff b) { return hipmr_ff_add(a, b); });
+  if (threadIdx.x == 0)
+    hipmr_partial[blockIdx.x] = __builtin_isfinite(hipmr_r.hi) ? (double)hipmr_r.hi + (double)hipmr_r.lo
+                                                               : (double)hipmr_r.hi;
+}
+)HIP";
+
+// Final fold of the FP64 block partials (Neumaier per thread, double-double
+// tree), times the per-tensor post scale; the norm finishes as sqrt / scale.
+const char* kCompS2 = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(const double* __restrict__ hipmr_partial, int hipmr_g, double hipmr_post,
+          const double* __restrict__ hipmr_scale64, double* __restrict__ hipmr_out)
+{
+  constexpr bool NORM = @@NORM@@, SCALED = @@SCALED@@;
+  double s = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < hipmr_g; k += @@BLOCK@@) {
+    const double v = hipmr_partial[k];
+    const double t = s + v;
+    if (__builtin_isfinite(t)) c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  hipmr_dd r = hipmr_two_sum_d(s, c);
+  r = hipmr_block_reduce_pair<@@BLOCK@@>(r, [](hipmr_dd a, hipmr_dd b) { return hipmr_dd_add(a, b); });
+  if (threadIdx.x == 0) {
+    const double total = __builtin_isfinite(r.hi) ? r.hi + r.lo : r.hi;
+    if constexpr (NORM && SCALED) *hipmr_out = hipmr_post * (sqrt(total) / *hipmr_scale64);
+    else if constexpr (NORM) *hipmr_out = hipmr_post * sqrt(total);
+    else *hipmr_out = hipmr_post * total;
+  }
+}
+)HIP";
+
+// Norm pass 1, final step: max |map| over the block partials, then the power
+// of two s = 2^-e (e = exponent of the max, clamped to [-126, 126]) that puts
+// the largest scaled magnitude in [1, 2).
+const char* kAmaxScale = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(const float* __restrict__ hipmr_partial, int hipmr_g, float* __restrict__ hipmr_scale_f,
+          double* __restrict__ hipmr_scale_d)
+{
+  float m = 0.0f;
+  for (int k = threadIdx.x; k < hipmr_g; k += @@BLOCK@@) m = hipmr_combine(m, hipmr_partial[k]);
+  m = hipmr_block_reduce<@@BLOCK@@>(m, 0.0f);
+  if (threadIdx.x == 0) {
+    float s = 1.0f;
+    if (m > 0.0f) {
+      int e = (int)((__float_as_uint(m) >> 23) & 0xffu) - 127;
+      e = e < -126 ? -126 : (e > 126 ? 126 : e);
+      s = __uint_as_float((unsigned int)(127 - e) << 23);
+    }
+    *hipmr_scale_f = s;
+    *hipmr_scale_d = (double)s;
+  }
+}
+)HIP";
+
 void replace_all(std::string& s, const std::string& key, const std::string& val) {
     size_t pos = 0;
     while ((pos = s.find(key, pos)) != std::string::npos) {
@@ -404,8 +696,7 @@ void replace_all(std::string& s, const std::string& key, const std::string& val)
     }
 }
 
-std::string combine_body(const Program& prog, const KernelSpec& spec) {
-    DType r = prog.sig.result;
+std::string combine_body(DType r, const KernelSpec& spec) {
     bool fp = r == DT_F32 || r == DT_F64;
     switch (canonical_combine(spec.combine)) {
         case Combine::Sum: return "a + b";
@@ -421,13 +712,28 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     const char* tmpl = nullptr;
     const char* tag = "";
     bool reduce = false;
+    bool comp = false;       // compensated helpers
+    DType acc = prog.sig.result;
+    std::string combine = spec.combine;
     switch (spec.kind) {
         case KernelKind::EwVector: tmpl = kEwVector; tag = "ew"; break;
         case KernelKind::EwScalar: tmpl = kEwScalar; tag = "ews"; break;
         case KernelKind::RedS1Vector: tmpl = kRedS1Vector; tag = "rs1"; reduce = true; break;
         case KernelKind::RedS1Scalar: tmpl = kRedS1Scalar; tag = "rs1s"; reduce = true; break;
         case KernelKind::RedS2: tmpl = kRedS2; tag = "rs2"; reduce = true; break;
+        case KernelKind::CompS1Vector:
+            tmpl = kCompS1Vector; tag = spec.square ? "nrm2" : "csum"; comp = true; break;
+        case KernelKind::CompS1Scalar:
+            tmpl = kCompS1Scalar; tag = spec.square ? "nrm2s" : "csums"; comp = true; break;
+        case KernelKind::CompS2: tmpl = kCompS2; tag = spec.norm ? "nrm2f" : "csumf"; comp = true; break;
+        case KernelKind::AmaxS1Vector:
+            tmpl = kRedS1Vector; tag = "amax"; reduce = true; acc = DT_F32; combine = "max"; break;
+        case KernelKind::AmaxS1Scalar:
+            tmpl = kRedS1Scalar; tag = "amaxs"; reduce = true; acc = DT_F32; combine = "max"; break;
+        case KernelKind::AmaxScale:
+            tmpl = kAmaxScale; tag = "ascale"; reduce = true; acc = DT_F32; combine = "max"; break;
     }
+    const bool amax = spec.kind == KernelKind::AmaxS1Vector || spec.kind == KernelKind::AmaxS1Scalar;
     std::string body = tmpl;
 
     // parameters in declaration order
@@ -447,8 +753,11 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     std::string decl_packs, loads, stores;
     for (const ArgDecl& a : prog.sig.args) {
         if (!a.pointer || !(a.read || a.written)) continue;
-        decl_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", V> hipmr_p_" +
-                      a.name + "[U]; ";
+        if (a.dtype == DT_FP8 && !a.written && spec.vec >= 4)
+            decl_packs += "hipmr_pack_fp8ro<V> hipmr_p_" + a.name + "[U]; ";
+        else
+            decl_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", V> hipmr_p_" +
+                          a.name + "[U]; ";
         if (!a.write_only)
             loads += "hipmr_load<NTL>(hipmr_p_" + a.name + "[hipmr_u], " + a.name + " + hipmr_off); ";
         if (a.written)
@@ -464,9 +773,17 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     replace_all(body, "@@STORES@@", stores);
     replace_all(body, "@@STMT@@", scalar_text);
     replace_all(body, "@@VSTMT@@", vector_text);
+    if (amax) {   // norm pass 1: |map| as float
+        scalar_text = "fabsf((float)(" + scalar_text + "))";
+        vector_text = "fabsf((float)(" + vector_text + "))";
+    }
     replace_all(body, "@@MAP@@", scalar_text);
     replace_all(body, "@@VMAP@@", vector_text);
-    replace_all(body, "@@NEUTRAL@@", spec.neutral.empty() ? "0" : spec.neutral);
+    replace_all(body, "@@NEUTRAL@@", amax ? "0.0f" : (spec.neutral.empty() ? "0" : spec.neutral));
+    replace_all(body, "@@SQUARE@@", spec.square ? "true" : "false");
+    replace_all(body, "@@RUNS@@", spec.exact_runs ? "true" : "false");
+    replace_all(body, "@@NORM@@", spec.norm ? "true" : "false");
+    replace_all(body, "@@SCALED@@", spec.scaled ? "true" : "false");
     replace_all(body, "@@IDX@@", spec.idx64 ? "long long" : "int");
     replace_all(body, "@@BLOCK@@", std::to_string(spec.block));
     replace_all(body, "@@IPT@@", std::to_string(spec.ipt));
@@ -477,14 +794,19 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     std::ostringstream src;
     src << "// generated by hipmr: " << tag << " kernel of \"" << prog.name << "\"\n";
     src << kPrelude;
+    std::string cbody;
     if (reduce) {
-        src << "typedef " << dtype_device_name(prog.sig.result) << " hipmr_acc;\n";
+        KernelSpec cs = spec;
+        cs.combine = combine;
+        cbody = combine_body(acc, cs);
+        src << "typedef " << dtype_device_name(acc) << " hipmr_acc;\n";
         src << "__device__ __forceinline__ hipmr_acc hipmr_combine(hipmr_acc a, hipmr_acc b) "
-               "{ return (hipmr_acc)(" << combine_body(prog, spec) << "); }\n";
+               "{ return (hipmr_acc)(" << cbody << "); }\n";
         src << kReduceHelpers;
     }
+    if (comp) src << kCompHelpers;
     // the symbol carries a hash of everything that shapes the kernel
-    std::string unnamed = (reduce ? combine_body(prog, spec) + "\n" : std::string()) + body;
+    std::string unnamed = cbody + "\n" + body;
     std::string key = sha256_hex(unnamed.data(), unnamed.size());
     std::string sym = prog.name + "_" + tag + "_" + key.substr(0, 8);
     replace_all(body, "@@KNAME@@", sym);

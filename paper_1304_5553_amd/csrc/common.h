@@ -98,6 +98,8 @@ struct LaunchCfg {
 // ---------------------------------------------------------------- codegen
 enum class KernelKind : int32_t {
     EwVector = 0, EwScalar = 1, RedS1Vector = 2, RedS1Scalar = 3, RedS2 = 4,
+    CompS1Vector = 5, CompS1Scalar = 6, CompS2 = 7, AmaxS1Vector = 8, AmaxS1Scalar = 9,
+    AmaxScale = 10,
 };
 
 struct KernelSpec {
@@ -110,6 +112,11 @@ struct KernelSpec {
     bool nt_stores = true;
     std::string combine;      // reduce kinds
     std::string neutral;
+    // precision extension
+    bool square = false;      // CompS1: accumulate map^2 (norm)
+    bool scaled = false;      // CompS1 / CompS2: apply the device-side power-of-two scale
+    bool exact_runs = false;  // CompS1: map is one FP8 load; sum runs of <= 64 exactly
+    bool norm = false;        // CompS2: finish as sqrt(sum) / scale
 };
 
 struct Program {                 // everything codegen needs about one handle

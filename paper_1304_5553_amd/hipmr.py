@@ -112,6 +112,10 @@ _SIGS = {
     "hipmr_reduce_ex": (_I32, [_VP, _CP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ,
                                ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_prepare_reduce": (_I32, [_VP, _CP, _CP]),
+    "hipmr_reduce_compensated": (_I32, [_VP, _I64, _VP, _D, _VP, _VP, _SZ,
+                                        ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_norm2": (_I32, [_VP, _I64, _VP, _D, _I32, _VP, _VP, _SZ,
+                           ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_last_error": (_CP, []),
     "hipmr_release": (None, [_VP]),
     "hipmr_get_handle_info": (_I32, [_VP, ctypes.POINTER(HandleInfo)]),
@@ -321,6 +325,44 @@ def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspac
                                  ctypes.c_void_p(workspace_buf.data_ptr()),
                                  workspace_buf.numel() * workspace_buf.element_size(),
                                  _config(config), s))
+    return out
+
+
+def _f64_out(out, args):
+    import torch
+    if out is not None:
+        return out
+    device = next((a.device for a in args if isinstance(a, torch.Tensor)), torch.device("cuda"))
+    return torch.empty((), dtype=torch.float64, device=device)
+
+
+def reduce_compensated(handle: Kernel, n, args, post_scale=1.0, out=None, workspace_buf=None,
+                       stream=None, config=None):
+    """Compensated float sum (FP64 result) = post_scale * sum map(i)."""
+    out = _f64_out(out, args)
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_reduce_compensated(handle.handle, int(n), ptrs, float(post_scale),
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(workspace_buf.data_ptr()),
+                                          workspace_buf.numel(), _config(config), s))
+    return out
+
+
+def norm2(handle: Kernel, n, args, post_scale=1.0, passes=2, out=None, workspace_buf=None,
+          stream=None, config=None):
+    """L2 norm (FP64 result) = post_scale * sqrt(sum map(i)^2); scaled two-pass by default."""
+    out = _f64_out(out, args)
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_norm2(handle.handle, int(n), ptrs, float(post_scale), int(passes),
+                             ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
+                             _config(config), s))
     return out
 
 
