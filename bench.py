@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--n", type=int, default=1 << 28)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extensions", action="store_true",
+                   help="skip the precision and batching measurements")
     p.add_argument("--cpu-sample", type=int, default=1 << 27,
                    help="elements per op for the oracle timing")
     p.add_argument("--ops", default="E1,E2,R1,R2,R3",
@@ -89,6 +91,122 @@ def cpu_baseline(x, y, k, sample):
             "kind": "oracle",
             "sample": f"first {m} elements of each of E1, E2, R1, R2, R3 "
                       f"({nbytes / 1e6:.0f} MB algorithmic) in {dt:.1f} s"}
+
+
+def _time_ms(torch, fn, reps, stream):
+    """Median per-call milliseconds of fn() over reps calls (HIP events on
+    the launch stream)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    fn()
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
+    """Compensated sum and scaled two-pass L2 norm at n = 2**27 per format.
+    `copies` rotated copies of the input (>= 4 x 134-268 MB) keep the working
+    set out of the 256 MB last-level cache."""
+    n = workloads.N_PRECISION
+    v64 = workloads.precision_values(n, "lognormal")
+    out = {}
+    for fmt in ("bfloat16", "float16", "fp8_e4m3"):
+        q = workloads.quantize(fmt, v64)
+        tdt = {"bfloat16": torch.bfloat16, "float16": torch.float16,
+               "fp8_e4m3": torch.float8_e4m3fn}[fmt]
+        host = torch.from_numpy(q.bits)
+        host = host.view(torch.int16 if host.element_size() == 2 else torch.uint8).view(tdt)
+        bufs = [host.to(dev) for _ in range(copies)]
+        k = hm.compile("x[i]", f"float: const {fmt} *x", name=f"bench_{fmt[:4]}")
+        o = torch.empty((), dtype=torch.float64, device=dev)
+        ws = hm.hipmr.workspace(hm.reduce_workspace_bytes(k, n), dev, stream.cuda_stream)
+        it = [0]
+
+        def nxt():
+            it[0] += 1
+            return bufs[it[0] % copies]
+        inv = 1.0 / q.scale
+        t_sum = _time_ms(torch, lambda: hm.reduce_compensated(k, n, [nxt()], inv, o, ws), reps, stream)
+        t_nrm = _time_ms(torch, lambda: hm.norm2(k, n, [nxt()], inv, 2, o, ws), reps, stream)
+        nbytes = n * host.element_size()
+        out[fmt] = {"sum_ms": round(t_sum, 4), "sum_GB/s": round(nbytes / t_sum / 1e6, 1),
+                    "norm2_ms": round(t_nrm, 4),
+                    "norm2_GB/s": round(2 * nbytes / t_nrm / 1e6, 1),
+                    "sum_symbols": k.last_symbols()}
+        del bufs
+        torch.cuda.empty_cache()
+    return {"n": n, "workload": "lognormal(0,3) x random sign, per-tensor power-of-two scale",
+            "bytes_note": "sum reads n*size once; the scaled norm reads it twice", "formats": out}
+
+
+def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
+    """4096 lognormal segments (62,032,791 float32): segmented sum, max and dot
+    as one graph replay of the persistent launch sequences, against one plain
+    launch pair per segment (eager, and captured in a graph)."""
+    offsets, x, y = workloads.segments()
+    nseg = len(offsets) - 1
+    total = int(offsets[-1])
+    od = torch.from_numpy(offsets).to(dev)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    ops = {"sum": ("x[i]", "a+b", "0", 4), "max": ("x[i]", "max(a,b)", "-INFINITY", 4),
+           "dot": ("x[i]*y[i]", "a+b", "0", 8)}
+    sig = "float: const float *x, const float *y"
+    ks = {op: hm.compile(m, sig, name=f"batch_{op}") for op, (m, _, _, _) in ops.items()}
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        outs = {op: torch.empty(nseg, device=dev) for op in ops}
+        wss = {op: torch.empty(hm.segmented_workspace_bytes(ks[op], nseg, total),
+                               dtype=torch.uint8, device=dev) for op in ops}
+        tuned = {}
+        for op, (m, comb, neu, _) in ops.items():
+            tuned[op] = hm.autotune_segmented(ks[op], comb, neu, od, total, [xd, yd], outs[op],
+                                              reps=3, workspace_buf=wss[op], stream=stream)
+
+        def issue():
+            for op, (m, comb, neu, _) in ops.items():
+                hm.reduce_segmented(ks[op], comb, neu, od, total, [xd, yd], outs[op],
+                                    workspace_buf=wss[op], stream=stream)
+        issue()
+        stream.synchronize()
+        graph = hm.Graph()
+        with graph.capture(stream):
+            issue()
+        t_batched = _time_ms(torch, lambda: graph.launch(stream), reps, stream)
+        t_eager_batched = _time_ms(torch, issue, reps, stream)
+        # baseline: one plain map-reduce (two launches) per segment and op
+        plain_out = torch.empty(nseg, device=dev)
+        ws1 = hm.hipmr.workspace(hm.reduce_workspace_bytes(ks["sum"], 1), dev, stream.cuda_stream)
+        views = [(int(a), int(b)) for a, b in zip(offsets[:-1], offsets[1:])]
+
+        def per_segment():
+            for op, (m, comb, neu, _) in ops.items():
+                k = ks[op]
+                for s, (a, b) in enumerate(views):
+                    hm.reduce(k, None, comb, neu, b - a, [xd[a:b], yd[a:b]], plain_out[s], ws1,
+                              stream=stream)
+        t_plain = _time_ms(torch, per_segment, baseline_reps, stream)
+        pgraph = hm.Graph()
+        with pgraph.capture(stream):
+            per_segment()
+        t_plain_graph = _time_ms(torch, lambda: pgraph.launch(stream), baseline_reps, stream)
+    nbytes = sum(total * b for (_, _, _, b) in ops.values())
+    res = {"nseg": nseg, "total_elements": total, "algorithmic_bytes": nbytes,
+           "batched_graph_ms": round(t_batched, 4),
+           "batched_graph_GB/s": round(nbytes / t_batched / 1e6, 1),
+           "batched_eager_ms": round(t_eager_batched, 4),
+           "per_segment_eager_ms": round(t_plain, 3),
+           "per_segment_graph_ms": round(t_plain_graph, 3),
+           "speedup_vs_per_segment": round(t_plain / t_batched, 1),
+           "speedup_vs_per_segment_graph": round(t_plain_graph / t_batched, 1),
+           "launches_batched": 3 * 3, "launches_per_segment": 3 * nseg * 2,
+           "tuned": tuned}
+    return res
 
 
 def main():
@@ -233,6 +351,13 @@ def main():
         "results": result,
         "wall_s_timed": round(wall, 3),
     }
+    if not args.no_extensions:
+        del xd, yd, kd, z
+        torch.cuda.empty_cache()
+        line["precision"] = bench_precision(torch, hm, workloads, dev, stream)
+        print("precision done", file=sys.stderr, flush=True)
+        line["batched"] = bench_batched(torch, hm, workloads, dev)
+        print("batched done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, k, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -107,6 +107,8 @@ typedef struct hipmr_launch_config {
 #define HIPMR_CFG_TEMPORAL         4  /* ordinary (temporal) loads and stores                */
 #define HIPMR_CFG_TEMPORAL_LOADS   8  /* ordinary loads, streaming stores                    */
 #define HIPMR_CFG_TEMPORAL_STORES 16  /* streaming loads, ordinary stores                    */
+#define HIPMR_CFG_SEG_GLOBAL      32  /* segmented: read the tile table from global memory
+                                         even when it would fit in LDS                       */
 
 /* ------------------------------------------------------------------ core */
 
@@ -180,6 +182,9 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char *map_expr, const char *c
  * hipmr_reduce (the paper's prepared invocation, section "The Basics of GPU
  * programming", declares argument types once for later calls).  No GPU needed. */
 hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char *combine_op, const char *neutral);
+/* Same, for one launch geometry (NULL = default). */
+hipmr_status hipmr_prepare_reduce_ex(hipmr_handle h, const char *combine_op, const char *neutral,
+                                     const hipmr_launch_config *cfg);
 
 /* Message of the last failure on this thread ("" if none).  Owned by the
  * library; valid until the next call on this thread. */
@@ -227,6 +232,70 @@ hipmr_status hipmr_reduce_compensated(hipmr_handle h, int64_t n, void *const *ar
 hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void *const *args, double post_scale,
                          int32_t passes, void *out, void *workspace, size_t workspace_bytes,
                          const hipmr_launch_config *cfg, void *stream);
+
+/* ------------------------------------------------------------------ batching extension */
+
+/* Bytes of device workspace hipmr_reduce_segmented / hipmr_autotune_segmented
+ * need for nseg segments over total_n elements (tile-start table plus one
+ * partial per tile at the smallest tile size any geometry can choose); 0 for
+ * an elementwise or invalid handle. */
+size_t hipmr_segmented_workspace_bytes(hipmr_handle h, int32_t nseg, int64_t total_n);
+
+/* Segmented map-reduce, many uneven segments in one launch sequence: for
+ * s in [0, nseg), d_out[s] = neutral (+) map(off[s]) (+) ... (+) map(off[s+1]-1),
+ * the map indexing the concatenated arrays with the global index i (and n =
+ * total_n).  Batching extension of the map-reduce (section "Map-Reduce").
+ *   d_offsets: device int64 array of nseg + 1 non-decreasing offsets into
+ *              [0, total_n]; values outside are clamped, a decreasing pair gives
+ *              an empty segment (never an out-of-bounds access).
+ *   d_out:     device array of nseg elements of the result type.
+ *   workspace: at least hipmr_segmented_workspace_bytes(h, nseg, total_n).
+ * Three launches on stream: a one-block planner turns the offsets into tiles
+ * (tile 0 of a segment holds its unaligned head and up to T body elements,
+ * later tiles T elements, T = 64 * vec * items_per_thread); a persistent
+ * kernel whose waves each reduce one tile at a time into a tile partial; one
+ * wave per segment folding its tiles in order.  A segment's result depends
+ * only on its own bounds and the geometry, so it is bitwise the same whatever
+ * the other segments are.  With cfg == NULL the geometry stored by
+ * hipmr_autotune_segmented for this handle, combine_op, neutral and size class
+ * is used, else the default.  Everything stays on the device, so the sequence
+ * can be captured once and replayed with new offset values.
+ * Errors: as hipmr_reduce; E_WORKSPACE for a short workspace. */
+hipmr_status hipmr_reduce_segmented(hipmr_handle h, const char *combine_op, const char *neutral,
+                                    int32_t nseg, const int64_t *d_offsets, int64_t total_n,
+                                    void *const *args, void *d_out, void *workspace,
+                                    size_t workspace_bytes, const hipmr_launch_config *cfg,
+                                    void *stream);
+
+/* Autotuner (section "Code Generation", "Automated Tuning"; and the future-work
+ * note on compiling a search's variants on all CPU cores): generates the
+ * candidate geometries (block 256/512, items_per_thread 1/2/4/8, 2-16 blocks
+ * per CU), compiles all their variants concurrently on host threads through
+ * the same hipRTC path, times each reps times on the caller's data with HIP
+ * events (median), stores the fastest for this handle, operation and size
+ * class in memory and in $HIPMR_CACHE_DIR, and returns it in *best.  Runs
+ * the operation (1 + reps) times per candidate, overwriting d_out / out. */
+hipmr_status hipmr_autotune_segmented(hipmr_handle h, const char *combine_op, const char *neutral,
+                                      int32_t nseg, const int64_t *d_offsets, int64_t total_n,
+                                      void *const *args, void *d_out, void *workspace,
+                                      size_t workspace_bytes, int32_t reps,
+                                      hipmr_launch_config *best, void *stream);
+hipmr_status hipmr_autotune_reduce(hipmr_handle h, const char *combine_op, const char *neutral,
+                                   int64_t n, void *const *args, void *out, void *workspace,
+                                   size_t workspace_bytes, int32_t reps, hipmr_launch_config *best,
+                                   void *stream);
+
+/* HIP graphs of launch sequences.  Every hipmr call between begin and end on
+ * this thread and stream is captured (not executed); end instantiates the
+ * graph; launch replays it with one call.  Run each operation once before
+ * capturing it so that its code objects are loaded (E_INVALID otherwise).
+ * The kernels write every output they own, so replays need no memory
+ * clearing nodes.  The null stream cannot be captured. */
+typedef struct hipmr_graph *hipmr_graph_t;
+hipmr_status hipmr_graph_begin_capture(void *stream);
+hipmr_status hipmr_graph_end_capture(void *stream, hipmr_graph_t *out);
+hipmr_status hipmr_graph_launch(hipmr_graph_t g, void *stream);
+void         hipmr_graph_destroy(hipmr_graph_t g);
 
 /* ------------------------------------------------------------------ introspection */
 

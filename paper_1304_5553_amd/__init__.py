@@ -8,7 +8,8 @@ hash.  This package is its thin Python binding; PyTorch provides device
 memory and streams only.
 """
 
-from .hipmr import (CFG_FORCE_SCALAR, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
+from .hipmr import (CFG_FORCE_SCALAR, Graph, autotune_reduce, autotune_segmented,
+                    reduce_segmented, segmented_workspace_bytes, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
                     ElementwiseKernel, HipError, HipmrError, InvalidError, Kernel, LaunchConfig,
                     MismatchError, ParseError, ReductionKernel, UnsupportedError, WorkspaceError,
                     cache_drop_memory, cache_stats, compile, elementwise, lib, prepare_reduce,
@@ -16,7 +17,8 @@ from .hipmr import (CFG_FORCE_SCALAR, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError
                     sha256_hex, torch_dtype)
 
 __all__ = ["ElementwiseKernel", "ReductionKernel", "Kernel", "compile", "elementwise", "reduce",
-           "reduce_compensated", "norm2",
+           "reduce_compensated", "norm2", "reduce_segmented", "segmented_workspace_bytes",
+           "autotune_segmented", "autotune_reduce", "Graph",
            "prepare_reduce", "reduce_workspace_bytes", "cache_stats", "cache_drop_memory",
            "sha256_hex", "selftest_compile", "lib", "torch_dtype", "LaunchConfig",
            "CFG_NONTEMPORAL", "CFG_TEMPORAL", "CFG_FORCE_SCALAR", "HipmrError", "InvalidError",

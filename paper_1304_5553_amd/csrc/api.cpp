@@ -8,35 +8,11 @@
 #include <cstring>
 #include <map>
 
-#include "common.h"
+#include "internal.h"
 
 using namespace hipmr;
 
-struct hipmr_kernel {
-    std::atomic<int> refs{1};
-    Program prog;
-    int default_vec = 4;
-    std::mutex mu;
-    std::map<std::string, std::shared_ptr<CodeObject>> variants;
-    std::string last_symbols;   // kernels of the most recent launch sequence
-};
-
-namespace {
-
-constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
-constexpr int kStage2Block = 256;
-// workspace layout: [0, 64 KiB) block partials; then the norm's scale as a
-// float (+0) and a double (+8)
-constexpr size_t kScaleOffset = (size_t)kMaxPartials * 8;
-constexpr size_t kWorkspaceBytes = kScaleOffset + 256;
-
-// Default geometry (overridable per call through hipmr_launch_config), from
-// sweeps on MI355X at n = 2^28: streaming reads reach their best rate with a
-// small resident grid (2 blocks of 256 threads per CU, 4 chunks of 16 bytes
-// in flight per thread and array); elementwise kernels, which mix reads and
-// writes, do best as one pass over a full grid (one chunk per thread).
-constexpr int kEwBlock = 256, kEwIpt = 1, kEwBlocksPerCu = 1 << 20;
-constexpr int kRedBlock = 256, kRedIpt = 4, kRedBlocksPerCu = 2;
+namespace hipmr {
 
 int default_vec_for(const Signature& sig) {
     int min_size = 0;
@@ -83,6 +59,7 @@ hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int v
     if (c->flags & HIPMR_CFG_TEMPORAL_LOADS) out->nt_loads = false;
     if (c->flags & HIPMR_CFG_TEMPORAL_STORES) out->nt_stores = false;
     out->force_scalar = (c->flags & HIPMR_CFG_FORCE_SCALAR) != 0;
+    out->seg_global = (c->flags & HIPMR_CFG_SEG_GLOBAL) != 0;
     return HIPMR_OK;
 }
 
@@ -91,7 +68,8 @@ std::string spec_key(const KernelSpec& s) {
            std::to_string(s.block) + "|" + std::to_string(s.ipt) + "|" + std::to_string(s.vec) +
            "|" + std::to_string(s.nt_loads) + std::to_string(s.nt_stores) + "|" +
            std::to_string(s.square) + std::to_string(s.scaled) + std::to_string(s.exact_runs) +
-           std::to_string(s.norm) + "|" + s.combine + "\x1f" + s.neutral;
+           std::to_string(s.norm) + "|" + std::to_string(s.lds_segs) + "|" + s.combine + "\x1f" +
+           s.neutral;
 }
 
 hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out) {
@@ -238,7 +216,7 @@ KernelSpec s2_spec(const char* combine, const char* neutral) {
     return s;
 }
 
-}  // namespace
+}  // namespace hipmr
 
 
 namespace {
@@ -464,16 +442,22 @@ size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n) {
     return kWorkspaceBytes;
 }
 
-hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char* combine, const char* neutral) {
+hipmr_status hipmr_prepare_reduce_ex(hipmr_handle h, const char* combine, const char* neutral,
+                                     const hipmr_launch_config* cfgp) {
     clear_error();
     if (!h || !combine || !neutral) return fail(HIPMR_E_INVALID, "NULL argument");
     if (!h->prog.sig.is_reduce) return fail(HIPMR_E_MISMATCH, "elementwise handle");
     LaunchCfg cfg;
-    resolve_cfg(nullptr, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
+    hipmr_status rs = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
+    if (rs != HIPMR_OK) return rs;
     std::shared_ptr<CodeObject> co;
     hipmr_status st = get_variant(h, s1_spec(h, h->prog.info.vectorizable, cfg, false, combine, neutral), &co);
     if (st != HIPMR_OK) return st;
     return get_variant(h, s2_spec(combine, neutral), &co);
+}
+
+hipmr_status hipmr_prepare_reduce(hipmr_handle h, const char* combine, const char* neutral) {
+    return hipmr_prepare_reduce_ex(h, combine, neutral, nullptr);
 }
 
 hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* combine,
@@ -490,6 +474,8 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* c
     if (!out) return fail(HIPMR_E_INVALID, "out is NULL");
     if (!workspace || workspace_bytes < hipmr_reduce_workspace_bytes(h, n))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_reduce_workspace_bytes()");
+    hipmr_launch_config tuned{};
+    if (!cfgp && tuned_config(h, "reduce", combine, neutral, n, &tuned)) cfgp = &tuned;
     LaunchCfg cfg;
     st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
     if (st != HIPMR_OK) return st;
@@ -673,6 +659,27 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
             }
             st = get_variant(h, s2_spec(c.combine, c.neutral), &co);
             ++built;
+            if (st == HIPMR_OK) {
+                // batching extension: planner, tile stage, per-segment stage
+                for (int lds : {0, 4096}) {
+                    for (KernelKind k : {KernelKind::SegPlan, KernelKind::SegS1, KernelKind::SegS2}) {
+                        KernelSpec q;
+                        q.kind = k;
+                        q.block = k == KernelKind::SegPlan ? 1024 : 256;
+                        q.ipt = k == KernelKind::SegS2 ? 1 : 4;
+                        q.vec = k == KernelKind::SegS2 ? 1 : h->default_vec;
+                        q.lds_segs = k == KernelKind::SegS1 ? lds : 0;
+                        if (k != KernelKind::SegPlan) {
+                            q.combine = c.combine;
+                            q.neutral = c.neutral;
+                        }
+                        st = get_variant(h, q, &co);
+                        if (st != HIPMR_OK) break;
+                        ++built;
+                    }
+                    if (st != HIPMR_OK) break;
+                }
+            }
             if (st == HIPMR_OK && h->prog.sig.result == DT_F32) {
                 // precision extension: compensated sum, norm passes, finishers
                 std::vector<KernelSpec> specs;

@@ -231,13 +231,13 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head)
 {
   typedef @@IDX@@ hipmr_idx;
-  constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
-  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
   // elements [0, head) precede the first aligned chunk; [t0, n) is the ragged tail
   const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
-  const long long hipmr_nc = (hipmr_n - hipmr_h) / V;
-  const long long hipmr_t0 = hipmr_h + hipmr_nc * V;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / HIPMR_V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * HIPMR_V;
   if (blockIdx.x == 0) {
     if ((long long)threadIdx.x < hipmr_h) {
       const hipmr_idx i = (hipmr_idx)threadIdx.x;
@@ -248,20 +248,20 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       { @@STMT@@; }
     }
   }
-  const long long hipmr_step = (long long)gridDim.x * (B * U);
-  long long hipmr_c0 = (long long)blockIdx.x * (B * U) + threadIdx.x;
-  for (; hipmr_c0 + (U - 1) * B < hipmr_nc; hipmr_c0 += hipmr_step) {
+  const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
+  long long hipmr_c0 = (long long)blockIdx.x * (HIPMR_B * HIPMR_U) + threadIdx.x;
+  for (; hipmr_c0 + (HIPMR_U - 1) * HIPMR_B < hipmr_nc; hipmr_c0 += hipmr_step) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
       @@LOADS@@
     }
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
 #pragma unroll
-      for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+      for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
         const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
         { @@VSTMT@@; }
       }
@@ -271,20 +271,20 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   if (hipmr_c0 < hipmr_nc) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
         @@LOADS@@
       }
     }
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
 #pragma unroll
-        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
           { @@VSTMT@@; }
         }
@@ -317,16 +317,16 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
           hipmr_acc* __restrict__ hipmr_partial)
 {
   typedef @@IDX@@ hipmr_idx;
-  constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
-  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
-  hipmr_acc hipmr_a[U];
+  hipmr_acc hipmr_a[HIPMR_U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) hipmr_a[u] = hipmr_neutral;
+  for (int u = 0; u < HIPMR_U; ++u) hipmr_a[u] = hipmr_neutral;
   const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
-  const long long hipmr_nc = (hipmr_n - hipmr_h) / V;
-  const long long hipmr_t0 = hipmr_h + hipmr_nc * V;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / HIPMR_V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * HIPMR_V;
   if (blockIdx.x == 0) {
     if ((long long)threadIdx.x < hipmr_h) {
       const hipmr_idx i = (hipmr_idx)threadIdx.x;
@@ -337,20 +337,20 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
     }
   }
-  const long long hipmr_step = (long long)gridDim.x * (B * U);
-  long long hipmr_c0 = (long long)blockIdx.x * (B * U) + threadIdx.x;
-  for (; hipmr_c0 + (U - 1) * B < hipmr_nc; hipmr_c0 += hipmr_step) {
+  const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
+  long long hipmr_c0 = (long long)blockIdx.x * (HIPMR_B * HIPMR_U) + threadIdx.x;
+  for (; hipmr_c0 + (HIPMR_U - 1) * HIPMR_B < hipmr_nc; hipmr_c0 += hipmr_step) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
       @@LOADS@@
     }
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
 #pragma unroll
-      for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+      for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
         const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
         hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@VMAP@@));
       }
@@ -359,28 +359,28 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   if (hipmr_c0 < hipmr_nc) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
         @@LOADS@@
       }
     }
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
 #pragma unroll
-        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
           hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@VMAP@@));
         }
       }
     }
   }
-  hipmr_acc hipmr_r = hipmr_fold<U>(hipmr_a);
-  hipmr_r = hipmr_block_reduce<B>(hipmr_r, hipmr_neutral);
+  hipmr_acc hipmr_r = hipmr_fold<HIPMR_U>(hipmr_a);
+  hipmr_r = hipmr_block_reduce<HIPMR_B>(hipmr_r, hipmr_neutral);
   if (threadIdx.x == 0) hipmr_partial[blockIdx.x] = hipmr_r;
 }
 )HIP";
@@ -521,45 +521,45 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
           double* __restrict__ hipmr_partial, const float* __restrict__ hipmr_scale_p)
 {
   typedef @@IDX@@ hipmr_idx;
-  constexpr int B = @@BLOCK@@, U = @@IPT@@, V = @@VEC@@;
-  constexpr bool NTL = @@NTL@@, NTS = @@NTS@@;
-  constexpr bool SQ = @@SQUARE@@, RUNS = @@RUNS@@, SCALED = @@SCALED@@;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  constexpr bool HIPMR_SQ = @@SQUARE@@, HIPMR_RUNS = @@RUNS@@, HIPMR_SCALED = @@SCALED@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
-  const float hipmr_sc = SCALED ? *hipmr_scale_p : 1.0f;
-  float hipmr_s[U], hipmr_e[U];
+  const float hipmr_sc = HIPMR_SCALED ? *hipmr_scale_p : 1.0f;
+  float hipmr_s[HIPMR_U], hipmr_e[HIPMR_U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) { hipmr_s[u] = 0.0f; hipmr_e[u] = 0.0f; }
+  for (int u = 0; u < HIPMR_U; ++u) { hipmr_s[u] = 0.0f; hipmr_e[u] = 0.0f; }
   const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
-  const long long hipmr_nc = (hipmr_n - hipmr_h) / V;
-  const long long hipmr_t0 = hipmr_h + hipmr_nc * V;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / HIPMR_V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * HIPMR_V;
   if (blockIdx.x == 0) {
     if ((long long)threadIdx.x < hipmr_h) {
       const hipmr_idx i = (hipmr_idx)threadIdx.x;
-      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<HIPMR_SQ>((float)(@@MAP@@), hipmr_sc));
     }
     if ((long long)threadIdx.x < hipmr_n - hipmr_t0) {
       const hipmr_idx i = (hipmr_idx)(hipmr_t0 + threadIdx.x);
-      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+      hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_term<HIPMR_SQ>((float)(@@MAP@@), hipmr_sc));
     }
   }
-  const long long hipmr_step = (long long)gridDim.x * (B * U);
-  long long hipmr_c0 = (long long)blockIdx.x * (B * U) + threadIdx.x;
-  for (; hipmr_c0 + (U - 1) * B < hipmr_nc; hipmr_c0 += hipmr_step) {
+  const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
+  long long hipmr_c0 = (long long)blockIdx.x * (HIPMR_B * HIPMR_U) + threadIdx.x;
+  for (; hipmr_c0 + (HIPMR_U - 1) * HIPMR_B < hipmr_nc; hipmr_c0 += hipmr_step) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
       @@LOADS@@
     }
-    if constexpr (RUNS) {
+    if constexpr (HIPMR_RUNS) {
       // every value is k * 2^-9 with |k| <= 229376: a float sum of at most
       // 64 of them is exact, so one compensated step per run suffices
       float hipmr_run = 0.0f;
 #pragma unroll
-      for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
 #pragma unroll
-        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
           hipmr_run += (float)(@@VMAP@@);
         }
@@ -567,47 +567,47 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       hipmr_kahan_add(hipmr_s[0], hipmr_e[0], hipmr_run);
     } else {
 #pragma unroll
-      for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * B) * V;
-        float hipmr_t[V];
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_h + (hipmr_c0 + hipmr_u * HIPMR_B) * HIPMR_V;
+        float hipmr_t[HIPMR_V];
 #pragma unroll
-        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
-          hipmr_t[hipmr_j] = hipmr_term<SQ>((float)(@@VMAP@@), hipmr_sc);
+          hipmr_t[hipmr_j] = hipmr_term<HIPMR_SQ>((float)(@@VMAP@@), hipmr_sc);
         }
-        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<V>(hipmr_t));
+        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<HIPMR_V>(hipmr_t));
       }
     }
   }
   if (hipmr_c0 < hipmr_nc) {
     @@DECL_PACKS@@
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
         @@LOADS@@
       }
     }
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_c0 + hipmr_u * B;
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       if (hipmr_c < hipmr_nc) {
-        const long long hipmr_off = hipmr_h + hipmr_c * V;
-        float hipmr_t[V];
+        const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
+        float hipmr_t[HIPMR_V];
 #pragma unroll
-        for (int hipmr_j = 0; hipmr_j < V; ++hipmr_j) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
-          hipmr_t[hipmr_j] = hipmr_term<SQ>((float)(@@VMAP@@), hipmr_sc);
+          hipmr_t[hipmr_j] = hipmr_term<HIPMR_SQ>((float)(@@VMAP@@), hipmr_sc);
         }
-        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<V>(hipmr_t));
+        hipmr_kahan_add(hipmr_s[hipmr_u], hipmr_e[hipmr_u], hipmr_chunk_sum<HIPMR_V>(hipmr_t));
       }
     }
   }
   hipmr_ff hipmr_r = {hipmr_s[0], -hipmr_e[0]};
 #pragma unroll
-  for (int u = 1; u < U; ++u) hipmr_r = hipmr_ff_add(hipmr_r, hipmr_ff{hipmr_s[u], -hipmr_e[u]});
-  hipmr_r = hipmr_block_reduce_pair<B>(hipmr_r, [](hipmr_ff a, hipmr_ff b) { return hipmr_ff_add(a, b); });
+  for (int u = 1; u < HIPMR_U; ++u) hipmr_r = hipmr_ff_add(hipmr_r, hipmr_ff{hipmr_s[u], -hipmr_e[u]});
+  hipmr_r = hipmr_block_reduce_pair<HIPMR_B>(hipmr_r, [](hipmr_ff a, hipmr_ff b) { return hipmr_ff_add(a, b); });
   if (threadIdx.x == 0)
     hipmr_partial[blockIdx.x] = __builtin_isfinite(hipmr_r.hi) ? (double)hipmr_r.hi + (double)hipmr_r.lo
                                                                : (double)hipmr_r.hi;
@@ -620,15 +620,15 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
           double* __restrict__ hipmr_partial, const float* __restrict__ hipmr_scale_p)
 {
   typedef @@IDX@@ hipmr_idx;
-  constexpr bool SQ = @@SQUARE@@, SCALED = @@SCALED@@;
+  constexpr bool HIPMR_SQ = @@SQUARE@@, HIPMR_SCALED = @@SCALED@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
-  const float hipmr_sc = SCALED ? *hipmr_scale_p : 1.0f;
+  const float hipmr_sc = HIPMR_SCALED ? *hipmr_scale_p : 1.0f;
   float hipmr_s = 0.0f, hipmr_cc = 0.0f;
   const long long hipmr_step = (long long)gridDim.x * @@BLOCK@@;
   for (long long hipmr_k = (long long)blockIdx.x * @@BLOCK@@ + threadIdx.x; hipmr_k < hipmr_n;
        hipmr_k += hipmr_step) {
     const hipmr_idx i = (hipmr_idx)hipmr_k;
-    hipmr_kahan_add(hipmr_s, hipmr_cc, hipmr_term<SQ>((float)(@@MAP@@), hipmr_sc));
+    hipmr_kahan_add(hipmr_s, hipmr_cc, hipmr_term<HIPMR_SQ>((float)(@@MAP@@), hipmr_sc));
   }
   hipmr_ff hipmr_r = {hipmr_s, -hipmr_cc};
   hipmr_r = hipmr_block_reduce_pair<@@BLOCK@@>(hipmr_r, [](hipmr_ff a, hipmr_ff b) { return hipmr_ff_add(a, b); });
@@ -688,6 +688,188 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
+
+// ------------------------------------------------------------ batching
+// Segments [off[s], off[s+1]) of the concatenated arrays are cut into tiles:
+// tile 0 of a segment holds its unaligned head plus up to T body elements,
+// later tiles T body elements each, where body elements start at the first
+// index congruent to `head` modulo V (every accessed array is 16-byte aligned
+// there) and T = 64 * V * IPT.  One wave reduces one tile.  The partition of
+// a segment depends only on its bounds, V and IPT, never on other segments.
+const char* kSegHelpers = R"HIP(
+__device__ __forceinline__ void hipmr_seg_bounds(const long long* __restrict__ off, int s,
+                                                 long long total, long long head, int V,
+                                                 long long& a, long long& b, long long& ab) {
+  a = off[s];
+  b = off[s + 1];
+  a = a < 0 ? 0 : (a > total ? total : a);
+  b = b < a ? a : (b > total ? total : b);
+  long long r = (head - a) % V;
+  if (r < 0) r += V;
+  ab = a + r < b ? a + r : b;
+}
+__device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long long ab, long long T) {
+  if (b == a) return 0;
+  const long long t = (b - ab + T - 1) / T;
+  return t < 1 ? 1 : (int)t;
+}
+)HIP";
+
+// Planner: tiles per segment and their exclusive prefix, one block.
+const char* kSegPlan = R"HIP(
+extern "C" __global__ void __launch_bounds__(1024)
+@@KNAME@@(const long long* __restrict__ hipmr_off, int hipmr_nseg, long long hipmr_total,
+          long long hipmr_head, int* __restrict__ hipmr_tile_start)
+{
+  constexpr int B = 1024, V = @@VEC@@;
+  constexpr long long T = 64LL * @@VEC@@ * @@IPT@@;
+  __shared__ int hipmr_wsum[B / 64];
+  __shared__ int hipmr_carry;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (threadIdx.x == 0) hipmr_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < hipmr_nseg; base += B) {
+    const int s = base + threadIdx.x;
+    int tiles = 0;
+    if (s < hipmr_nseg) {
+      long long a, b, ab;
+      hipmr_seg_bounds(hipmr_off, s, hipmr_total, hipmr_head, V, a, b, ab);
+      tiles = hipmr_seg_tiles(a, b, ab, T);
+    }
+    int x = tiles;                               // inclusive scan in the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (l >= d) x += y;
+    }
+    if (l == 63) hipmr_wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {                                // scan of the wave totals
+      int v = l < B / 64 ? hipmr_wsum[l] : 0;
+#pragma unroll
+      for (int d = 1; d < B / 64; d <<= 1) {
+        const int y = __shfl_up(v, d, 64);
+        if (l >= d) v += y;
+      }
+      if (l < B / 64) hipmr_wsum[l] = v;
+    }
+    __syncthreads();
+    const int excl = hipmr_carry + (w > 0 ? hipmr_wsum[w - 1] : 0) + x - tiles;
+    if (s < hipmr_nseg) hipmr_tile_start[s] = excl;
+    __syncthreads();
+    if (threadIdx.x == B - 1) hipmr_carry = excl + tiles;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) hipmr_tile_start[hipmr_nseg] = hipmr_carry;
+}
+)HIP";
+
+// Persistent stage 1: waves take tiles t = wave, wave + nwaves, ...
+const char* kSegS1 = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_total, long long hipmr_head,
+          const long long* __restrict__ hipmr_offsets, int hipmr_nseg,
+          const int* __restrict__ hipmr_tile_start, hipmr_acc* __restrict__ hipmr_tpart)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@, HIPMR_LDS_SEGS = @@LDS_SEGS@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  constexpr long long HIPMR_T = 64LL * HIPMR_V * HIPMR_U;
+  const hipmr_idx n = (hipmr_idx)hipmr_total;
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  const int hipmr_lane = threadIdx.x & 63;
+  // the tile-start table, staged in LDS when it fits (checked here as well,
+  // so a table larger than the LDS copy is always read from global memory)
+  __shared__ int hipmr_ts_lds[HIPMR_LDS_SEGS > 0 ? HIPMR_LDS_SEGS : 1];
+  const bool hipmr_in_lds = HIPMR_LDS_SEGS > 0 && hipmr_nseg < HIPMR_LDS_SEGS;
+  if (hipmr_in_lds) {
+    for (int hipmr_k = threadIdx.x; hipmr_k <= hipmr_nseg; hipmr_k += HIPMR_B)
+      hipmr_ts_lds[hipmr_k] = hipmr_tile_start[hipmr_k];
+    __syncthreads();
+  }
+  auto hipmr_ts = [&](int hipmr_k) -> int {
+    return hipmr_in_lds ? hipmr_ts_lds[hipmr_k] : hipmr_tile_start[hipmr_k];
+  };
+  const int hipmr_total_tiles = hipmr_ts(hipmr_nseg);
+  const int hipmr_nwaves = gridDim.x * (HIPMR_B / 64);
+  for (int hipmr_t = blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6); hipmr_t < hipmr_total_tiles; hipmr_t += hipmr_nwaves) {
+    // segment of the tile: the last s with tile_start[s] <= tile (64-way ballot search)
+    int hipmr_lo = 0, hipmr_hi = hipmr_nseg - 1;
+    while (hipmr_lo < hipmr_hi) {
+      const int hipmr_step = (hipmr_hi - hipmr_lo + 64) / 64;
+      const int hipmr_cand = hipmr_lo + hipmr_lane * hipmr_step;
+      const bool hipmr_pred = hipmr_cand <= hipmr_hi && hipmr_ts(hipmr_cand) <= hipmr_t;
+      const unsigned long long hipmr_m = __ballot(hipmr_pred);
+      const int hipmr_k = 63 - __builtin_clzll(hipmr_m);
+      hipmr_lo = hipmr_lo + hipmr_k * hipmr_step;
+      hipmr_hi = hipmr_lo + hipmr_step - 1 < hipmr_hi ? hipmr_lo + hipmr_step - 1 : hipmr_hi;
+    }
+    const int hipmr_s = hipmr_lo;
+    long long hipmr_sa, hipmr_sb, hipmr_sab;
+    hipmr_seg_bounds(hipmr_offsets, hipmr_s, hipmr_total, hipmr_head, HIPMR_V, hipmr_sa, hipmr_sb, hipmr_sab);
+    const long long hipmr_k = hipmr_t - hipmr_ts(hipmr_s);
+    const long long hipmr_tstart = hipmr_k == 0 ? hipmr_sa : hipmr_sab + hipmr_k * HIPMR_T;
+    const long long hipmr_hend = hipmr_k == 0 ? hipmr_sab : hipmr_tstart;
+    const long long hipmr_te = hipmr_sab + (hipmr_k + 1) * HIPMR_T < hipmr_sb ? hipmr_sab + (hipmr_k + 1) * HIPMR_T : hipmr_sb;
+    const long long hipmr_nch = hipmr_te > hipmr_hend ? (hipmr_te - hipmr_hend) / HIPMR_V : 0;
+    const long long hipmr_tail = hipmr_hend + hipmr_nch * HIPMR_V;
+    hipmr_acc hipmr_a[HIPMR_U];
+#pragma unroll
+    for (int u = 0; u < HIPMR_U; ++u) hipmr_a[u] = hipmr_neutral;
+    if (hipmr_lane < hipmr_hend - hipmr_tstart) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_tstart + hipmr_lane);
+      hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
+    }
+    @@DECL_PACKS@@
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_lane + 64 * hipmr_u;
+      if (hipmr_c < hipmr_nch) {
+        const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
+        @@LOADS@@
+      }
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_lane + 64 * hipmr_u;
+      if (hipmr_c < hipmr_nch) {
+        const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@VMAP@@));
+        }
+      }
+    }
+    if (hipmr_lane < hipmr_te - hipmr_tail) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_tail + hipmr_lane);
+      hipmr_a[HIPMR_U - 1] = hipmr_combine(hipmr_a[HIPMR_U - 1], (hipmr_acc)(@@MAP@@));
+    }
+    hipmr_acc hipmr_r = hipmr_fold<HIPMR_U>(hipmr_a);
+    hipmr_r = hipmr_block_reduce<64>(hipmr_r, hipmr_neutral);
+    if (hipmr_lane == 0) hipmr_tpart[hipmr_t] = hipmr_r;
+  }
+}
+)HIP";
+
+// Stage 2: one wave per segment folds its tile partials in tile order.
+const char* kSegS2 = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(const int* __restrict__ hipmr_tile_start, int hipmr_nseg,
+          const hipmr_acc* __restrict__ hipmr_tpart, hipmr_acc* __restrict__ hipmr_out)
+{
+  const int s = blockIdx.x * (@@BLOCK@@ / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (s >= hipmr_nseg) return;                  // whole waves only
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  hipmr_acc r = hipmr_neutral;
+  const int t1 = hipmr_tile_start[s + 1];
+  for (int t = hipmr_tile_start[s] + lane; t < t1; t += 64) r = hipmr_combine(r, hipmr_tpart[t]);
+  r = hipmr_block_reduce<64>(r, hipmr_neutral);
+  if (lane == 0) hipmr_out[s] = r;
+}
+)HIP";
+
 void replace_all(std::string& s, const std::string& key, const std::string& val) {
     size_t pos = 0;
     while ((pos = s.find(key, pos)) != std::string::npos) {
@@ -732,7 +914,11 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             tmpl = kRedS1Scalar; tag = "amaxs"; reduce = true; acc = DT_F32; combine = "max"; break;
         case KernelKind::AmaxScale:
             tmpl = kAmaxScale; tag = "ascale"; reduce = true; acc = DT_F32; combine = "max"; break;
+        case KernelKind::SegPlan: tmpl = kSegPlan; tag = "segplan"; break;
+        case KernelKind::SegS1: tmpl = kSegS1; tag = "seg1"; reduce = true; break;
+        case KernelKind::SegS2: tmpl = kSegS2; tag = "seg2"; reduce = true; break;
     }
+    const bool seg = spec.kind == KernelKind::SegPlan || spec.kind == KernelKind::SegS1;
     const bool amax = spec.kind == KernelKind::AmaxS1Vector || spec.kind == KernelKind::AmaxS1Scalar;
     std::string body = tmpl;
 
@@ -754,14 +940,14 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     for (const ArgDecl& a : prog.sig.args) {
         if (!a.pointer || !(a.read || a.written)) continue;
         if (a.dtype == DT_FP8 && !a.written && spec.vec >= 4)
-            decl_packs += "hipmr_pack_fp8ro<V> hipmr_p_" + a.name + "[U]; ";
+            decl_packs += "hipmr_pack_fp8ro<HIPMR_V> hipmr_p_" + a.name + "[HIPMR_U]; ";
         else
-            decl_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", V> hipmr_p_" +
-                          a.name + "[U]; ";
+            decl_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", HIPMR_V> hipmr_p_" +
+                          a.name + "[HIPMR_U]; ";
         if (!a.write_only)
-            loads += "hipmr_load<NTL>(hipmr_p_" + a.name + "[hipmr_u], " + a.name + " + hipmr_off); ";
+            loads += "hipmr_load<HIPMR_NTL>(hipmr_p_" + a.name + "[hipmr_u], " + a.name + " + hipmr_off); ";
         if (a.written)
-            stores += "hipmr_store<NTS>(" + a.name + " + hipmr_off, hipmr_p_" + a.name + "[hipmr_u]); ";
+            stores += "hipmr_store<HIPMR_NTS>(" + a.name + " + hipmr_off, hipmr_p_" + a.name + "[hipmr_u]); ";
     }
 
     std::string scalar_text = join_tokens(prog.toks);
@@ -784,6 +970,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     replace_all(body, "@@RUNS@@", spec.exact_runs ? "true" : "false");
     replace_all(body, "@@NORM@@", spec.norm ? "true" : "false");
     replace_all(body, "@@SCALED@@", spec.scaled ? "true" : "false");
+    replace_all(body, "@@LDS_SEGS@@", std::to_string(spec.lds_segs));
     replace_all(body, "@@IDX@@", spec.idx64 ? "long long" : "int");
     replace_all(body, "@@BLOCK@@", std::to_string(spec.block));
     replace_all(body, "@@IPT@@", std::to_string(spec.ipt));
@@ -805,6 +992,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
         src << kReduceHelpers;
     }
     if (comp) src << kCompHelpers;
+    if (seg) src << kSegHelpers;
     // the symbol carries a hash of everything that shapes the kernel
     std::string unnamed = cbody + "\n" + body;
     std::string key = sha256_hex(unnamed.data(), unnamed.size());

@@ -93,13 +93,14 @@ struct LaunchCfg {
     bool nt_loads = true;   // streaming (non-temporal) loads
     bool nt_stores = true;  // streaming (non-temporal) stores
     bool force_scalar = false;
+    bool seg_global = false;  // segmented: tile table in global memory
 };
 
 // ---------------------------------------------------------------- codegen
 enum class KernelKind : int32_t {
     EwVector = 0, EwScalar = 1, RedS1Vector = 2, RedS1Scalar = 3, RedS2 = 4,
     CompS1Vector = 5, CompS1Scalar = 6, CompS2 = 7, AmaxS1Vector = 8, AmaxS1Scalar = 9,
-    AmaxScale = 10,
+    AmaxScale = 10, SegPlan = 11, SegS1 = 12, SegS2 = 13,
 };
 
 struct KernelSpec {
@@ -117,6 +118,8 @@ struct KernelSpec {
     bool scaled = false;      // CompS1 / CompS2: apply the device-side power-of-two scale
     bool exact_runs = false;  // CompS1: map is one FP8 load; sum runs of <= 64 exactly
     bool norm = false;        // CompS2: finish as sqrt(sum) / scale
+    // batching extension
+    int lds_segs = 0;         // SegS1: tile-start table held in LDS (capacity), 0 = global
 };
 
 struct Program {                 // everything codegen needs about one handle
@@ -153,5 +156,9 @@ hipmr_status launch(void* fn, unsigned grid, unsigned block, void** params, void
 
 void cache_stats(hipmr_cache_stats* out);
 void cache_drop_memory();
+
+// True between hipmr_graph_begin_capture and hipmr_graph_end_capture on this
+// thread: code objects must already be loaded then.
+bool capturing_now();
 
 }  // namespace hipmr

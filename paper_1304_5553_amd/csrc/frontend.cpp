@@ -92,6 +92,14 @@ std::string trim(const std::string& s) {
 }
 
 bool is_ident_start(char c) { return std::isalpha((unsigned char)c) || c == '_'; }
+
+// Generated kernels name everything they declare hipmr_* / HIPMR_*.
+bool has_reserved_prefix(const std::string& name) {
+    if (name.size() < 6) return false;
+    std::string p = name.substr(0, 6);
+    for (char& c : p) c = (char)std::tolower((unsigned char)c);
+    return p == "hipmr_";
+}
 bool is_ident_char(char c) { return std::isalnum((unsigned char)c) || c == '_'; }
 
 }  // namespace
@@ -168,8 +176,8 @@ hipmr_status parse_signature(const std::string& text, Signature* out) {
         a.dtype = it->second;
         if (a.name == "i" || a.name == "n")
             return fail(HIPMR_E_PARSE, "signature: '" + a.name + "' is reserved (formal index / length)");
-        if (a.name.rfind("hipmr_", 0) == 0)
-            return fail(HIPMR_E_PARSE, "signature: names starting with hipmr_ are reserved");
+        if (has_reserved_prefix(a.name))
+            return fail(HIPMR_E_PARSE, "signature: names starting with hipmr_ (any case) are reserved");
         if (!seen.insert(a.name).second)
             return fail(HIPMR_E_PARSE, "signature: duplicate argument '" + a.name + "'");
         out->args.push_back(a);
@@ -275,8 +283,8 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
             if (t.text == "for" || t.text == "while" || t.text == "do" || t.text == "switch") saw_loop = true;
             if ((t.text == "break" || t.text == "continue") && !saw_loop)
                 return fail(HIPMR_E_UNSUPPORTED, "expression: '" + t.text + "' outside a loop");
-            if (t.text.rfind("hipmr_", 0) == 0)
-                return fail(HIPMR_E_PARSE, "expression: names starting with hipmr_ are reserved");
+            if (has_reserved_prefix(t.text))
+                return fail(HIPMR_E_PARSE, "expression: names starting with hipmr_ (any case) are reserved");
         }
         if (t.kind != Token::Punct) continue;
         char c = t.text[0];

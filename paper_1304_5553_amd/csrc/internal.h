@@ -1,0 +1,52 @@
+// Internals shared by the translation units that implement the C ABI:
+// the handle object, launch-geometry defaults and the variant cache.
+#pragma once
+
+#include <atomic>
+#include <map>
+
+#include "common.h"
+
+struct hipmr_kernel {
+    std::atomic<int> refs{1};
+    hipmr::Program prog;
+    int default_vec = 4;
+    std::mutex mu;
+    std::map<std::string, std::shared_ptr<hipmr::CodeObject>> variants;
+    std::string last_symbols;                        // kernels of the most recent call
+    std::map<std::string, hipmr_launch_config> tuned;  // autotuned geometry per operation
+};
+
+namespace hipmr {
+
+constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
+constexpr int kStage2Block = 256;
+// reduce workspace layout: [0, 64 KiB) block partials; then the norm's scale
+// as a float (+0) and a double (+8)
+constexpr size_t kScaleOffset = (size_t)kMaxPartials * 8;
+constexpr size_t kWorkspaceBytes = kScaleOffset + 256;
+
+// Default geometry (overridable per call through hipmr_launch_config), from
+// sweeps on MI355X at n = 2^28: streaming reads reach their best rate with a
+// small resident grid (2 blocks of 256 threads per CU, 4 chunks of 16 bytes
+// in flight per thread and array); elementwise kernels, which mix reads and
+// writes, do best as one pass over a full grid (one chunk per thread).
+constexpr int kEwBlock = 256, kEwIpt = 1, kEwBlocksPerCu = 1 << 20;
+constexpr int kRedBlock = 256, kRedIpt = 4, kRedBlocksPerCu = 2;
+
+hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int vec,
+                         int blocks_per_cu, LaunchCfg* out);
+hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out);
+hipmr_status variant_function(hipmr_kernel* h, const KernelSpec& spec, void** fn,
+                              std::string* syms);
+void set_last_symbols(hipmr_kernel* h, const std::string& syms);
+// element offset at which every accessed array is aligned for VEC-element
+// chunk loads, or -1
+long long common_head(const hipmr_kernel* h, void* const* args, int vec);
+hipmr_status check_args(hipmr_kernel* h, int64_t n, void* const* args);
+int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap);
+// geometry stored by the autotuner for (op, combine, neutral, size class of n)
+bool tuned_config(hipmr_kernel* h, const char* op, const char* combine, const char* neutral,
+                  long long n, hipmr_launch_config* out);
+
+}  // namespace hipmr

@@ -202,6 +202,9 @@ hipmr_status get_function(CodeObject& co, void** fn) {
     if (dev < 0 || dev >= kMaxDevices) return fail(HIPMR_E_HIP, "device index out of range");
     std::lock_guard<std::mutex> lk(co.mu);
     if (!co.function[dev]) {
+        if (capturing_now())
+            return fail(HIPMR_E_INVALID, "kernel " + co.symbol + " is not loaded on this device yet: "
+                                         "run the operation once before capturing it in a graph");
         hipModule_t m;
         e = hipModuleLoadData(&m, co.image.data());
         if (e != hipSuccess)

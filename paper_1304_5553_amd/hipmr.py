@@ -31,7 +31,7 @@ DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "i
                BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3"}
 
 CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
-CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES = 8, 16
+CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES, CFG_SEG_GLOBAL = 8, 16, 32
 
 
 class HipmrError(RuntimeError):
@@ -112,6 +112,18 @@ _SIGS = {
     "hipmr_reduce_ex": (_I32, [_VP, _CP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ,
                                ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_prepare_reduce": (_I32, [_VP, _CP, _CP]),
+    "hipmr_prepare_reduce_ex": (_I32, [_VP, _CP, _CP, ctypes.POINTER(LaunchConfig)]),
+    "hipmr_segmented_workspace_bytes": (_SZ, [_VP, _I32, _I64]),
+    "hipmr_reduce_segmented": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ,
+                                      ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_autotune_segmented": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ, _I32,
+                                        ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_autotune_reduce": (_I32, [_VP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ, _I32,
+                                     ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_graph_begin_capture": (_I32, [_VP]),
+    "hipmr_graph_end_capture": (_I32, [_VP, ctypes.POINTER(_VP)]),
+    "hipmr_graph_launch": (_I32, [_VP, _VP]),
+    "hipmr_graph_destroy": (None, [_VP]),
     "hipmr_reduce_compensated": (_I32, [_VP, _I64, _VP, _D, _VP, _VP, _SZ,
                                         ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_norm2": (_I32, [_VP, _I64, _VP, _D, _I32, _VP, _VP, _SZ,
@@ -364,6 +376,91 @@ def norm2(handle: Kernel, n, args, post_scale=1.0, passes=2, out=None, workspace
                              ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
                              _config(config), s))
     return out
+
+
+def segmented_workspace_bytes(handle: Kernel, nseg, total_n):
+    return lib().hipmr_segmented_workspace_bytes(handle.handle, int(nseg), int(total_n))
+
+
+def reduce_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, args, out,
+                     workspace_buf=None, stream=None, config=None):
+    """out[s] = fold of map(i) over i in [offsets[s], offsets[s+1]) (device
+    int64 offsets, nseg + 1 of them)."""
+    nseg = offsets.numel() - 1
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_reduce_segmented(handle.handle, combine_op.encode(), neutral.encode(), nseg,
+                                        ctypes.c_void_p(offsets.data_ptr()), int(total_n), ptrs,
+                                        ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(workspace_buf.data_ptr()),
+                                        workspace_buf.numel(), _config(config), s))
+    return out
+
+
+def autotune_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, args, out,
+                       reps=10, workspace_buf=None, stream=None):
+    """Times the candidate geometries on this data and stores the fastest;
+    returns it as a dict."""
+    nseg = offsets.numel() - 1
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    best = LaunchConfig()
+    _check(lib().hipmr_autotune_segmented(handle.handle, combine_op.encode(), neutral.encode(), nseg,
+                                          ctypes.c_void_p(offsets.data_ptr()), int(total_n), ptrs,
+                                          ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(workspace_buf.data_ptr()),
+                                          workspace_buf.numel(), int(reps), ctypes.byref(best), s))
+    return {f: getattr(best, f) for f, _ in LaunchConfig._fields_}
+
+
+def autotune_reduce(handle: Kernel, combine_op, neutral, n, args, out, reps=10,
+                    workspace_buf=None, stream=None):
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    best = LaunchConfig()
+    _check(lib().hipmr_autotune_reduce(handle.handle, combine_op.encode(), neutral.encode(), int(n),
+                                       ptrs, ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(workspace_buf.data_ptr()),
+                                       workspace_buf.numel(), int(reps), ctypes.byref(best), s))
+    return {f: getattr(best, f) for f, _ in LaunchConfig._fields_}
+
+
+class Graph:
+    """Captures the hipmr calls issued inside ``with graph.capture(stream):``
+    into a HIP graph; ``graph.launch(stream)`` replays them."""
+
+    def __init__(self):
+        self._g = _VP()
+
+    def capture(self, stream):
+        graph = self
+
+        class _Ctx:
+            def __enter__(self_inner):
+                graph._stream = _stream_ptr(stream)
+                _check(lib().hipmr_graph_begin_capture(graph._stream))
+                return graph
+
+            def __exit__(self_inner, exc_type, exc, tb):
+                st = lib().hipmr_graph_end_capture(graph._stream, ctypes.byref(graph._g))
+                if exc_type is None:
+                    _check(st)
+                return False
+        return _Ctx()
+
+    def launch(self, stream=None):
+        _check(lib().hipmr_graph_launch(self._g, _stream_ptr(stream)))
+
+    def __del__(self):
+        if getattr(self, "_g", None) is not None and self._g.value and _lib is not None:
+            _lib.hipmr_graph_destroy(self._g)
+            self._g = None
 
 
 def prepare_reduce(handle: Kernel, combine_op, neutral):

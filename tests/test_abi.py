@@ -49,7 +49,7 @@ def test_classifier_read_write_sets():
     k = hm.compile("if (x[i] > 0) z[i] = 1; else z[i] = 2", "float *z, const float *x")
     assert k.vectorizable
     src = k.source(0)
-    assert "hipmr_load<NTL>(hipmr_p_z" in src          # conditional write: z is loaded first
+    assert "hipmr_load<HIPMR_NTL>(hipmr_p_z" in src          # conditional write: z is loaded first
     k = hm.compile("z[i] = x[i + 1]", "float *z, const float *x")
     assert not k.vectorizable
     k = hm.compile("q[i] = x[i]", "fp8_e4m3 *q, const bfloat16 *x")
@@ -63,7 +63,7 @@ def test_generated_source_shape():
     assert 'extern "C" __global__' in src and "__launch_bounds__(256)" in src
     assert re.search(r"lin_ew_[0-9a-f]{8}\(", src)
     assert "hipmr_p_x[hipmr_u].v[hipmr_j]" in src
-    assert "hipmr_load<NTL>(hipmr_p_z" not in src       # write-only: never loaded
+    assert "hipmr_load<HIPMR_NTL>(hipmr_p_z" not in src       # write-only: never loaded
     r = hm.compile("x[i]", "float: const float *x", name="mx")
     s1 = r.source(2, "max(a,b)", "-INFINITY")
     assert "__builtin_elementwise_maximum(a, b)" in s1 and "hipmr_block_reduce" in s1
