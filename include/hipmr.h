@@ -297,6 +297,99 @@ hipmr_status hipmr_graph_end_capture(void *stream, hipmr_graph_t *out);
 hipmr_status hipmr_graph_launch(hipmr_graph_t g, void *stream);
 void         hipmr_graph_destroy(hipmr_graph_t g);
 
+/* ------------------------------------------------------------------ serving extension */
+
+/* Map-reduce job templates of the request loop (each over float32 or
+ * bfloat16 arrays of n elements; the result is one double):
+ *   SUM        sum x[i]                  DOT        sum x[i]*y[i]
+ *   NORM2      sqrt(sum x[i]^2)          MAX        max x[i] (IEEE maximum; -inf for n = 0)
+ *   AXPBY_SUM  sum (a*x[i] + b*y[i])     COUNT_POS  #{i : x[i] > 0}
+ *   SUMSQ      sum x[i]^2                WMEAN      (sum w[i]*x[i]) / (sum w[i])
+ * Lanes accumulate in float, tile partials are float pairs, each job's tiles
+ * are folded in FP64 in tile order. */
+#define HIPMR_JOB_SUM        0
+#define HIPMR_JOB_DOT        1
+#define HIPMR_JOB_NORM2      2
+#define HIPMR_JOB_MAX        3
+#define HIPMR_JOB_AXPBY_SUM  4
+#define HIPMR_JOB_COUNT_POS  5
+#define HIPMR_JOB_SUMSQ      6
+#define HIPMR_JOB_WMEAN      7
+
+typedef struct hipmr_sjob {
+    const void *x, *y, *w;   /* device arrays (y: DOT, AXPBY_SUM; w: WMEAN; others may be NULL) */
+    int64_t n;               /* elements                                                       */
+    int32_t tmpl;            /* HIPMR_JOB_*                                                     */
+    int32_t dtype;           /* HIPMR_F32 or HIPMR_BF16                                         */
+    int64_t arrival_ns;      /* run_schedule: arrival time relative to the call (non-decreasing) */
+    double *out;             /* device pointer to one double                                    */
+    float a, b;              /* AXPBY_SUM coefficients                                          */
+} hipmr_sjob;
+
+typedef struct hipmr_server_config {
+    uint64_t hbm_budget_bytes;   /* bytes (inputs + output) of admitted, unfinished jobs; 0: 64 GiB */
+    int32_t nstreams;            /* batches in flight, one stream each (1..16); 0: 4                */
+    int32_t max_batch_jobs;      /* jobs per batch (1..4096; 1 = one launch pair per job); 0: 1024  */
+    int32_t max_batch_tiles;     /* tiles (1024 float32 / 2048 bfloat16 elements) per batch; 0: 2^18 */
+    int32_t blocks_per_cu;       /* persistent grid of the tile kernel; 0: 8                        */
+} hipmr_server_config;
+
+typedef struct hipmr_completion {
+    uint64_t ticket;         /* submit: its ticket; run_schedule: the job's index                */
+    int32_t status;          /* HIPMR_OK, or the code the job was rejected with                  */
+    int32_t batch_jobs;      /* jobs in the batch that carried it                                */
+    int64_t arrival_ns;      /* run_schedule: relative to the call; submit: server clock         */
+    int64_t launch_ns;       /* when its batch was launched                                      */
+    int64_t done_ns;         /* when the loop saw the batch complete (result visible on the host) */
+} hipmr_completion;
+
+typedef struct hipmr_server *hipmr_server_t;
+
+/* Device workspace of a server (per stream: job descriptors and tile
+ * partials), owned by the caller for the server's lifetime. */
+size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
+
+/* Serving extension of the map-reduce: starts a request loop on a host thread
+ * for the current device.  The loop releases arrivals, admits them in arrival
+ * order while the bytes of admitted, unfinished jobs stay within the budget,
+ * packs admitted jobs into one batch per free stream (continuous batching:
+ * jobs that arrive while others run join the next batch on a free stream) and
+ * launches it as two run-time compiled kernels: a persistent kernel whose
+ * waves take fixed-size tiles of any job (wave-uniform switch over template x
+ * dtype) and one wave per job folding its tiles.  A job's tiles depend only on
+ * the job, so its result is bitwise the same alone or in any mix.  Completion
+ * is observed with one event per batch.  Inputs stay resident: jobs name
+ * device arrays.  Errors: E_INVALID (config), E_WORKSPACE, E_COMPILE, E_HIP. */
+hipmr_status hipmr_server_create(const hipmr_server_config *cfg, void *workspace,
+                                 size_t workspace_bytes, hipmr_server_t *out);
+
+/* Submits one job now.  Invalid jobs are rejected here (E_INVALID,
+ * E_UNSUPPORTED; E_BUDGET for a job that can never fit the budget) and never
+ * packed.  *ticket identifies its completion in hipmr_server_poll. */
+hipmr_status hipmr_server_submit(hipmr_server_t s, const hipmr_sjob *job, uint64_t *ticket);
+
+/* Copies up to cap completions of submitted jobs into done; *ndone receives
+ * the count.  Reports a launch failure of the loop as its status. */
+hipmr_status hipmr_server_poll(hipmr_server_t s, hipmr_completion *done, int32_t cap,
+                               int32_t *ndone);
+
+/* Waits until every submitted job has completed. */
+hipmr_status hipmr_server_wait_idle(hipmr_server_t s);
+
+/* Open-loop replay: job k arrives at (call time + jobs[k].arrival_ns) and is
+ * handled by the loop like a submission; returns when all have completed,
+ * done[k] describing job k (rejected jobs carry their status and are never
+ * packed).  Latency of job k = done[k].done_ns - done[k].arrival_ns. */
+hipmr_status hipmr_server_run_schedule(hipmr_server_t s, const hipmr_sjob *jobs, int32_t njobs,
+                                       hipmr_completion *done);
+
+/* Stops the loop after the submitted work completes and frees its resources
+ * (not the caller's workspace). */
+void hipmr_server_destroy(hipmr_server_t s);
+
+/* The server clock (monotonic nanoseconds). */
+int64_t hipmr_server_now_ns(void);
+
 /* ------------------------------------------------------------------ introspection */
 
 typedef struct hipmr_handle_info {

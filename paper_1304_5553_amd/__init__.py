@@ -8,7 +8,7 @@ hash.  This package is its thin Python binding; PyTorch provides device
 memory and streams only.
 """
 
-from .hipmr import (CFG_FORCE_SCALAR, Graph, autotune_reduce, autotune_segmented,
+from .hipmr import (JOB_NAMES, CFG_FORCE_SCALAR, Graph, Server, autotune_reduce, autotune_segmented,
                     reduce_segmented, segmented_workspace_bytes, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
                     ElementwiseKernel, HipError, HipmrError, InvalidError, Kernel, LaunchConfig,
                     MismatchError, ParseError, ReductionKernel, UnsupportedError, WorkspaceError,
@@ -18,7 +18,7 @@ from .hipmr import (CFG_FORCE_SCALAR, Graph, autotune_reduce, autotune_segmented
 
 __all__ = ["ElementwiseKernel", "ReductionKernel", "Kernel", "compile", "elementwise", "reduce",
            "reduce_compensated", "norm2", "reduce_segmented", "segmented_workspace_bytes",
-           "autotune_segmented", "autotune_reduce", "Graph",
+           "autotune_segmented", "autotune_reduce", "Graph", "Server", "JOB_NAMES",
            "prepare_reduce", "reduce_workspace_bytes", "cache_stats", "cache_drop_memory",
            "sha256_hex", "selftest_compile", "lib", "torch_dtype", "LaunchConfig",
            "CFG_NONTEMPORAL", "CFG_TEMPORAL", "CFG_FORCE_SCALAR", "HipmrError", "InvalidError",

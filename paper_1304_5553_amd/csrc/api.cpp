@@ -727,6 +727,12 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         hipmr_release(h);
         if (st != HIPMR_OK) return st;
     }
+    {   // the serving loop's kernels
+        hipmr_status st2;
+        auto co = get_or_build(serve_source("hipmr_serve"), "hipmr_serve_s1", &st2);
+        if (!co) return st2;
+        ++built;
+    }
     if (count) *count = built;
     return HIPMR_OK;
 }

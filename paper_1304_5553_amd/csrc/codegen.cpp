@@ -890,6 +890,8 @@ std::string combine_body(DType r, const KernelSpec& spec) {
 
 }  // namespace
 
+const char* device_prelude() { return kPrelude; }
+
 std::string render(const Program& prog, const KernelSpec& spec, std::string* symbol) {
     const char* tmpl = nullptr;
     const char* tag = "";

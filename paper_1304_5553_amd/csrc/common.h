@@ -130,6 +130,10 @@ struct Program {                 // everything codegen needs about one handle
     ExprInfo info;
 };
 
+// Device helpers every generated module starts with (storage formats, chunk
+// loads and stores).
+const char* device_prelude();
+
 // Renders the full device source (prelude + one kernel) and its symbol name.
 std::string render(const Program& prog, const KernelSpec& spec, std::string* symbol);
 
@@ -142,6 +146,7 @@ std::shared_ptr<CodeObject> get_or_build(const std::string& source, const std::s
                                          hipmr_status* status);
 
 const std::string& code_object_symbol(const CodeObject& co);
+const std::string& code_object_image(const CodeObject& co);
 
 // hipFunction_t (as void*) of the code object on the current device; loads the
 // module on first use on that device.

@@ -49,4 +49,7 @@ int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap)
 bool tuned_config(hipmr_kernel* h, const char* op, const char* combine, const char* neutral,
                   long long n, hipmr_launch_config* out);
 
+// device source of the serving loop's kernels
+std::string serve_source(const std::string& prefix);
+
 }  // namespace hipmr

@@ -245,6 +245,7 @@ hipmr_status launch(void* fn, unsigned grid, unsigned block, void** params, void
 }
 
 const std::string& code_object_symbol(const CodeObject& co) { return co.symbol; }
+const std::string& code_object_image(const CodeObject& co) { return co.image; }
 
 void cache_stats(hipmr_cache_stats* out) {
     out->memory_hits = g_mem_hits.load();

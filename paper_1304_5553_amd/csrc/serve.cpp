@@ -1,0 +1,755 @@
+// Serving extension: a request loop for map-reduce jobs with continuous
+// batching.
+//
+// Jobs are map-reduce requests of one of eight templates over flat float32 or
+// bfloat16 arrays that stay resident on the device:
+//   sum, dot, L2 norm, max, axpby-then-sum, count(x > 0), sum of squares and
+//   weighted mean.
+// A host thread owns the loop:
+//   - arrivals are released at their scheduled time;
+//   - they are admitted while the bytes of unfinished jobs stay within the HBM
+//     budget;
+//   - admitted jobs are packed into one batch per free stream slot (up to k
+//     batches in flight);
+//   - a batch is two launches of run-time compiled kernels:
+//       1. a persistent kernel whose waves take fixed-size tiles of any job in
+//          the batch (a wave-uniform switch over template x dtype);
+//       2. one wave per job folding that job's tile partials in order and
+//          finishing the job (sqrt, ratio);
+//   - completion is observed through an event per batch.
+// A job's tiles depend only on the job (its length, dtype and alignment), so
+// its result is bitwise the same alone or in any mix.  With max_batch_jobs
+// = 1 the loop issues one launch pair per job with the descriptor passed by
+// value: the baseline.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+
+#include "internal.h"
+
+using namespace hipmr;
+
+namespace {
+
+constexpr int kServeBlock = 256;
+constexpr int kMaxBatchJobs = 4096;      // LDS table of job tile offsets
+
+// Device descriptor of one job (64 bytes; the layout matches the device-side
+// hipmr_sjob struct in the kernels below).
+struct DevJob {
+    const void* x;
+    const void* y;
+    const void* w;
+    long long n;
+    int tmpl;
+    int dtype;
+    int tile0;
+    int head;
+    double* out;
+    float a, b;
+};
+static_assert(sizeof(DevJob) == 64, "job descriptor layout");
+
+const char* kServeKernels = R"HIP(
+struct hipmr_sjob {
+  const void* x; const void* y; const void* w;
+  long long n;
+  int tmpl, dtype, tile0, head;
+  double* out;
+  float a, b;
+};
+
+// One element's contribution of template TMPL to the accumulators (s0, s1).
+template <int TMPL>
+__device__ __forceinline__ void hipmr_job_elem(float& s0, float& s1, float x, float y, float w,
+                                               float a, float b) {
+  if constexpr (TMPL == 0) s0 += x;                                   // sum
+  else if constexpr (TMPL == 1) s0 += x * y;                          // dot
+  else if constexpr (TMPL == 2) s0 += x * x;                          // L2 norm (sqrt at the end)
+  else if constexpr (TMPL == 3) s0 = __builtin_elementwise_maximum(s0, x);   // max
+  else if constexpr (TMPL == 4) s0 += a * x + b * y;                  // axpby, then sum
+  else if constexpr (TMPL == 5) s0 += x > 0.0f ? 1.0f : 0.0f;         // count(x > 0)
+  else if constexpr (TMPL == 6) s0 += x * x;                          // sum of squares
+  else { s0 += w * x; s1 += w; }                                      // weighted mean
+}
+
+template <int TMPL>
+__device__ __forceinline__ float hipmr_job_comb(float a, float b) {
+  if constexpr (TMPL == 3) return __builtin_elementwise_maximum(a, b);
+  else return a + b;
+}
+
+// Tile k of job J: tile 0 holds the unaligned head and up to TT aligned
+// elements, later tiles TT elements; lanes keep U chunks of V elements.
+template <int TMPL, typename T, int V, int U>
+__device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long k, int lane) {
+  constexpr long long TT = 64LL * V * U;
+  constexpr bool NY = TMPL == 1 || TMPL == 4, NW = TMPL == 7;
+  const T* X = (const T*)J.x;
+  const T* Y = (const T*)J.y;
+  const T* W = (const T*)J.w;
+  const long long n = J.n;
+  const bool vec_ok = J.head >= 0;
+  const long long ab = vec_ok ? (J.head < n ? J.head : n) : 0;
+  const long long ts = k == 0 ? 0 : ab + k * TT;
+  const long long te = ab + (k + 1) * TT < n ? ab + (k + 1) * TT : n;
+  const float neutral = TMPL == 3 ? -__builtin_huge_valf() : 0.0f;
+  float s0[U], s1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) { s0[u] = neutral; s1[u] = 0.0f; }
+  if (!vec_ok) {                         // arrays without a common alignment
+    for (long long e = ts + lane; e < te; e += 64)
+      hipmr_job_elem<TMPL>(s0[0], s1[0], (float)X[e], NY ? (float)Y[e] : 0.0f,
+                           NW ? (float)W[e] : 0.0f, J.a, J.b);
+  } else {
+    const long long hend = k == 0 ? ab : ts;
+    const long long nch = te > hend ? (te - hend) / V : 0;
+    const long long tail = hend + nch * V;
+    if (lane < hend - ts) {
+      const long long e = ts + lane;
+      hipmr_job_elem<TMPL>(s0[0], s1[0], (float)X[e], NY ? (float)Y[e] : 0.0f,
+                           NW ? (float)W[e] : 0.0f, J.a, J.b);
+    }
+    hipmr_pack<T, V> px[U], py[U], pw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long c = lane + 64 * u;
+      if (c < nch) {
+        const long long off = hend + c * V;
+        hipmr_load<true>(px[u], X + off);
+        if constexpr (NY) hipmr_load<true>(py[u], Y + off);
+        if constexpr (NW) hipmr_load<true>(pw[u], W + off);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long c = lane + 64 * u;
+      if (c < nch) {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          hipmr_job_elem<TMPL>(s0[u], s1[u], (float)px[u].v[j], NY ? (float)py[u].v[j] : 0.0f,
+                               NW ? (float)pw[u].v[j] : 0.0f, J.a, J.b);
+      }
+    }
+    if (lane < te - tail) {
+      const long long e = tail + lane;
+      hipmr_job_elem<TMPL>(s0[U - 1], s1[U - 1], (float)X[e], NY ? (float)Y[e] : 0.0f,
+                           NW ? (float)W[e] : 0.0f, J.a, J.b);
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < U; s *= 2) {
+#pragma unroll
+    for (int u = 0; u + s < U; u += 2 * s) {
+      s0[u] = hipmr_job_comb<TMPL>(s0[u], s0[u + s]);
+      s1[u] += s1[u + s];
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    s0[0] = hipmr_job_comb<TMPL>(s0[0], __shfl_xor(s0[0], m, 64));
+    s1[0] += __shfl_xor(s1[0], m, 64);
+  }
+  return make_float2(s0[0], s1[0]);
+}
+
+constexpr int HIPMR_TILE_F32 = 64 * 4 * 4, HIPMR_TILE_BF16 = 64 * 8 * 4;
+
+__device__ __forceinline__ float2 hipmr_job_dispatch(const hipmr_sjob& J, long long k, int lane) {
+  const bool bf = J.dtype == @@BF16CODE@@;
+  switch (J.tmpl * 2 + (bf ? 1 : 0)) {
+    case 0: return hipmr_job_tile<0, float, 4, 4>(J, k, lane);
+    case 1: return hipmr_job_tile<0, hipmr_bf16, 8, 4>(J, k, lane);
+    case 2: return hipmr_job_tile<1, float, 4, 4>(J, k, lane);
+    case 3: return hipmr_job_tile<1, hipmr_bf16, 8, 4>(J, k, lane);
+    case 4: return hipmr_job_tile<2, float, 4, 4>(J, k, lane);
+    case 5: return hipmr_job_tile<2, hipmr_bf16, 8, 4>(J, k, lane);
+    case 6: return hipmr_job_tile<3, float, 4, 4>(J, k, lane);
+    case 7: return hipmr_job_tile<3, hipmr_bf16, 8, 4>(J, k, lane);
+    case 8: return hipmr_job_tile<4, float, 4, 4>(J, k, lane);
+    case 9: return hipmr_job_tile<4, hipmr_bf16, 8, 4>(J, k, lane);
+    case 10: return hipmr_job_tile<5, float, 4, 4>(J, k, lane);
+    case 11: return hipmr_job_tile<5, hipmr_bf16, 8, 4>(J, k, lane);
+    case 12: return hipmr_job_tile<6, float, 4, 4>(J, k, lane);
+    case 13: return hipmr_job_tile<6, hipmr_bf16, 8, 4>(J, k, lane);
+    case 14: return hipmr_job_tile<7, float, 4, 4>(J, k, lane);
+    default: return hipmr_job_tile<7, hipmr_bf16, 8, 4>(J, k, lane);
+  }
+}
+
+// Final fold of one job's tile partials (in tile order, FP64) and its finish.
+__device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, int t1,
+                                                 const float2* __restrict__ tpart, int lane) {
+  const bool mx = J.tmpl == 3;
+  double a0 = mx ? -__builtin_huge_val() : 0.0, a1 = 0.0;
+  for (int t = t0 + lane; t < t1; t += 64) {
+    const float2 p = tpart[t];
+    a0 = mx ? __builtin_elementwise_maximum(a0, (double)p.x) : a0 + (double)p.x;
+    a1 += (double)p.y;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double o0 = __shfl_xor(a0, m, 64), o1 = __shfl_xor(a1, m, 64);
+    a0 = mx ? __builtin_elementwise_maximum(a0, o0) : a0 + o0;
+    a1 += o1;
+  }
+  if (lane == 0) {
+    double r = a0;
+    if (J.tmpl == 2) r = sqrt(a0);
+    else if (J.tmpl == 7) r = a0 / a1;
+    *J.out = r;
+  }
+}
+
+__device__ __forceinline__ int hipmr_job_tiles(const hipmr_sjob& J) {
+  if (J.n <= 0) return 0;
+  const long long tt = J.dtype == @@BF16CODE@@ ? HIPMR_TILE_BF16 : HIPMR_TILE_F32;
+  const long long ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
+  const long long t = (J.n - ab + tt - 1) / tt;
+  return t < 1 ? 1 : (int)t;
+}
+
+// Batched stage 1: persistent waves over the batch's tiles.
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_s1(const hipmr_sjob* __restrict__ jobs, int njobs, int total_tiles,
+              float2* __restrict__ tpart)
+{
+  __shared__ int hipmr_t0[@@MAXJ@@];
+  for (int k = threadIdx.x; k < njobs; k += 256) hipmr_t0[k] = jobs[k].tile0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int nwaves = gridDim.x * 4;
+  for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < total_tiles; t += nwaves) {
+    int lo = 0, hi = njobs - 1;                 // the last job with tile0 <= t
+    while (lo < hi) {
+      const int step = (hi - lo + 64) / 64;
+      const int cand = lo + lane * step;
+      const bool pred = cand <= hi && hipmr_t0[cand] <= t;
+      const unsigned long long m = __ballot(pred);
+      lo = lo + (63 - __builtin_clzll(m)) * step;
+      hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+    }
+    const hipmr_sjob J = jobs[lo];
+    const float2 r = hipmr_job_dispatch(J, t - J.tile0, lane);
+    if (lane == 0) tpart[t] = r;
+  }
+}
+
+// Batched stage 2: one wave per job.
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_s2(const hipmr_sjob* __restrict__ jobs, int njobs, int total_tiles,
+              const float2* __restrict__ tpart)
+{
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= njobs) return;
+  const hipmr_sjob J = jobs[j];
+  const int t1 = j + 1 < njobs ? jobs[j + 1].tile0 : total_tiles;
+  hipmr_job_finish(J, J.tile0, t1, tpart, threadIdx.x & 63);
+}
+
+// One job, descriptor by value: the one-launch-pair-per-job path.
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_one1(hipmr_sjob J, float2* __restrict__ tpart)
+{
+  const int lane = threadIdx.x & 63;
+  const int tiles = hipmr_job_tiles(J);
+  for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < tiles; t += gridDim.x * 4) {
+    const float2 r = hipmr_job_dispatch(J, t, lane);
+    if (lane == 0) tpart[t] = r;
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(64)
+@@PREFIX@@_one2(hipmr_sjob J, const float2* __restrict__ tpart)
+{
+  hipmr_job_finish(J, 0, hipmr_job_tiles(J), tpart, threadIdx.x & 63);
+}
+)HIP";
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int tile_elems(int32_t dtype) { return dtype == HIPMR_BF16 ? 64 * 8 * 4 : 64 * 4 * 4; }
+
+bool needs_y(int32_t tmpl) { return tmpl == HIPMR_JOB_DOT || tmpl == HIPMR_JOB_AXPBY_SUM; }
+bool needs_w(int32_t tmpl) { return tmpl == HIPMR_JOB_WMEAN; }
+
+// Element offset at which all of the job's arrays are 16-byte aligned, or -1.
+int job_head(const hipmr_sjob& j) {
+    const uintptr_t es = j.dtype == HIPMR_BF16 ? 2 : 4;
+    const int vec = (int)(16 / es);
+    const void* ptrs[3] = {j.x, needs_y(j.tmpl) ? j.y : nullptr, needs_w(j.tmpl) ? j.w : nullptr};
+    for (int h = 0; h < vec; ++h) {
+        bool ok = true;
+        for (const void* p : ptrs) {
+            if (!p) continue;
+            uintptr_t a = (uintptr_t)p;
+            if (a % es != 0 || (a + h * es) % 16 != 0) ok = false;
+        }
+        if (ok) return h;
+    }
+    return -1;
+}
+
+int job_tiles(const hipmr_sjob& j, int head) {
+    if (j.n <= 0) return 0;
+    const long long tt = tile_elems(j.dtype);
+    const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
+    const long long t = (j.n - ab + tt - 1) / tt;
+    return (int)std::max<long long>(t, 1);
+}
+
+uint64_t job_bytes(const hipmr_sjob& j) {
+    const uint64_t es = j.dtype == HIPMR_BF16 ? 2 : 4;
+    const uint64_t arrays = 1 + (needs_y(j.tmpl) ? 1 : 0) + (needs_w(j.tmpl) ? 1 : 0);
+    return (uint64_t)std::max<int64_t>(j.n, 0) * es * arrays + 8;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t slot_bytes(const hipmr_server_config& c) {
+    return align256((size_t)c.max_batch_jobs * sizeof(DevJob)) + align256((size_t)c.max_batch_tiles * 8);
+}
+
+hipmr_server_config resolved(const hipmr_server_config* in) {
+    hipmr_server_config c{};
+    if (in) c = *in;
+    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = 64ull << 30;
+    if (c.nstreams == 0) c.nstreams = 4;
+    if (c.max_batch_jobs == 0) c.max_batch_jobs = 1024;
+    if (c.max_batch_tiles == 0) c.max_batch_tiles = 1 << 18;
+    if (c.blocks_per_cu == 0) c.blocks_per_cu = 8;
+    return c;
+}
+
+}  // namespace
+
+namespace hipmr {
+
+// Device source of the serving kernels, specialised by keyword replacement.
+std::string serve_source(const std::string& prefix) {
+    std::string src = std::string("// generated by hipmr: serving kernels\n") + device_prelude() + kServeKernels;
+    auto rep = [&](const std::string& key, const std::string& val) {
+        size_t pos = 0;
+        while ((pos = src.find(key, pos)) != std::string::npos) {
+            src.replace(pos, key.size(), val);
+            pos += val.size();
+        }
+    };
+    rep("@@PREFIX@@", prefix);
+    rep("@@MAXJ@@", std::to_string(kMaxBatchJobs));
+    rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
+    return src;
+}
+
+}  // namespace hipmr
+
+struct hipmr_server {
+    hipmr_server_config cfg{};
+    int device = 0;
+    std::shared_ptr<CodeObject> co;
+    hipModule_t module = nullptr;
+    hipFunction_t f_s1 = nullptr, f_s2 = nullptr, f_one1 = nullptr, f_one2 = nullptr;
+    std::string prefix;
+    int cus = 256;
+
+    struct Pending {
+        hipmr_sjob job;
+        uint64_t ticket;
+        int64_t arrival_ns;
+        uint64_t bytes;
+        int tiles;
+        int head;
+    };
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        DevJob* host_desc = nullptr;    // pinned host memory
+        DevJob* dev_desc = nullptr;     // in the caller's workspace
+        void* tpart = nullptr;          // in the caller's workspace
+        std::vector<Pending> jobs;
+        int64_t launch_ns = 0;
+        bool busy = false;
+    };
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> incoming;       // submitted, not yet seen by the loop
+    std::deque<Pending> waiting;        // arrived, not yet admitted (loop thread only)
+    std::vector<hipmr_completion> finished;   // for poll
+    uint64_t next_ticket = 1;
+    uint64_t admitted = 0;              // bytes of admitted, unfinished jobs
+    int64_t unfinished = 0;             // submitted, not completed
+
+    // open-loop schedule replay
+    const hipmr_sjob* sched = nullptr;
+    int32_t sched_n = 0, sched_next = 0, sched_done = 0;
+    int64_t sched_t0 = 0;
+    hipmr_completion* sched_out = nullptr;
+
+    std::atomic<bool> stop{false};
+    hipmr_status worker_status = HIPMR_OK;
+    std::string worker_error;
+    std::thread worker;
+
+    void complete(const Pending& p, int32_t status, int32_t batch_jobs, int64_t launch, int64_t done) {
+        hipmr_completion c{};
+        c.ticket = p.ticket;
+        c.status = status;
+        c.batch_jobs = batch_jobs;
+        c.arrival_ns = p.arrival_ns;
+        c.launch_ns = launch;
+        c.done_ns = done;
+        std::lock_guard<std::mutex> lk(mu);
+        if (sched_out && p.ticket >= 1ull << 62) {
+            sched_out[p.ticket - (1ull << 62)] = c;
+            ++sched_done;
+        } else {
+            finished.push_back(c);
+        }
+        --unfinished;
+        cv_done.notify_all();
+    }
+
+    hipmr_status launch_batch(Slot& s) {
+        const int nj = (int)s.jobs.size();
+        if (cfg.max_batch_jobs == 1) {
+            const Pending& p = s.jobs[0];
+            DevJob d{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
+                     p.job.out, p.job.a, p.job.b};
+            int grid = std::max(1, std::min(cfg.blocks_per_cu * cus, (p.tiles + 3) / 4));
+            void* a1[2] = {&d, &s.tpart};
+            hipError_t e = hipModuleLaunchKernel(f_one1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
+            if (e == hipSuccess) {
+                void* a2[2] = {&d, &s.tpart};
+                e = hipModuleLaunchKernel(f_one2, 1, 1, 1, 64, 1, 1, 0, s.stream, a2, nullptr);
+            }
+            if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
+        } else {
+            int tile0 = 0;
+            for (int k = 0; k < nj; ++k) {
+                const Pending& p = s.jobs[k];
+                s.host_desc[k] = DevJob{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype,
+                                        tile0, p.head, p.job.out, p.job.a, p.job.b};
+                tile0 += p.tiles;
+            }
+            int total = tile0;
+            hipError_t e = hipMemcpyAsync(s.dev_desc, s.host_desc, (size_t)nj * sizeof(DevJob),
+                                          hipMemcpyHostToDevice, s.stream);
+            int grid = std::max(1, std::min(cfg.blocks_per_cu * cus, (total + 3) / 4));
+            void* a1[4] = {&s.dev_desc, (void*)&nj, &total, &s.tpart};
+            if (e == hipSuccess)
+                e = hipModuleLaunchKernel(f_s1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
+            void* a2[4] = {&s.dev_desc, (void*)&nj, &total, &s.tpart};
+            if (e == hipSuccess)
+                e = hipModuleLaunchKernel(f_s2, (nj + 3) / 4, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+            if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
+        }
+        hipError_t e = hipEventRecord(s.done, s.stream);
+        if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
+        s.launch_ns = now_ns();
+        s.busy = true;
+        return HIPMR_OK;
+    }
+
+    // One pass of the loop; returns true if it did anything.
+    bool step() {
+        bool progressed = false;
+        const int64_t t = now_ns();
+        {   // arrivals
+            std::lock_guard<std::mutex> lk(mu);
+            while (!incoming.empty()) {
+                waiting.push_back(incoming.front());
+                incoming.pop_front();
+                progressed = true;
+            }
+            while (sched && sched_next < sched_n && sched_t0 + sched[sched_next].arrival_ns <= t) {
+                const hipmr_sjob& j = sched[sched_next];
+                Pending p{j, (1ull << 62) + (uint64_t)sched_next, sched_t0 + j.arrival_ns, job_bytes(j), 0,
+                          job_head(j)};
+                p.tiles = job_tiles(j, p.head);
+                waiting.push_back(p);
+                ++sched_next;
+                progressed = true;
+            }
+        }
+        // completions
+        for (Slot& s : slots) {
+            if (!s.busy) continue;
+            hipError_t q = hipEventQuery(s.done);
+            if (q == hipErrorNotReady) continue;
+            const int64_t done = now_ns();
+            const int32_t st = q == hipSuccess ? HIPMR_OK : HIPMR_E_HIP;
+            for (const Pending& p : s.jobs) {
+                admitted -= p.bytes;
+                complete(p, st, (int32_t)s.jobs.size(), s.launch_ns, done);
+            }
+            s.jobs.clear();
+            s.busy = false;
+            progressed = true;
+        }
+        // admission + packing into free slots
+        for (Slot& s : slots) {
+            if (s.busy || waiting.empty()) continue;
+            int tiles = 0;
+            while (!waiting.empty() && (int)s.jobs.size() < cfg.max_batch_jobs) {
+                const Pending& p = waiting.front();
+                if (admitted + p.bytes > cfg.hbm_budget_bytes) break;
+                if (!s.jobs.empty() && tiles + p.tiles > cfg.max_batch_tiles) break;
+                admitted += p.bytes;
+                tiles += p.tiles;
+                s.jobs.push_back(p);
+                waiting.pop_front();
+            }
+            if (s.jobs.empty()) break;       // budget full: wait for completions
+            hipmr_status st = launch_batch(s);
+            if (st != HIPMR_OK) {
+                worker_status = st;
+                worker_error = last_error();
+                for (const Pending& p : s.jobs) {
+                    admitted -= p.bytes;
+                    complete(p, st, (int32_t)s.jobs.size(), now_ns(), now_ns());
+                }
+                s.jobs.clear();
+            }
+            progressed = true;
+        }
+        return progressed;
+    }
+
+    void loop() {
+        if (hipSetDevice(device) != hipSuccess) {
+            worker_status = HIPMR_E_HIP;
+            worker_error = "hipSetDevice failed in the serving thread";
+            return;
+        }
+        while (true) {
+            bool progressed = step();
+            if (stop.load()) {
+                bool busy = false;
+                for (Slot& s : slots) busy |= s.busy;
+                std::lock_guard<std::mutex> lk(mu);
+                if (!busy && incoming.empty() && waiting.empty()) break;
+            }
+            if (!progressed) {
+                bool busy = false;
+                for (Slot& s : slots) busy |= s.busy;
+                std::unique_lock<std::mutex> lk(mu);
+                bool sched_pending = sched && sched_next < sched_n;
+                if (!busy && waiting.empty() && incoming.empty() && !sched_pending) {
+                    cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                } else {
+                    lk.unlock();
+                    std::this_thread::yield();
+                }
+            }
+        }
+    }
+};
+
+namespace {
+
+hipmr_status validate_job(const hipmr_server* s, const hipmr_sjob* j) {
+    if (!j) return fail(HIPMR_E_INVALID, "NULL job");
+    if (j->tmpl < 0 || j->tmpl > HIPMR_JOB_WMEAN) return fail(HIPMR_E_INVALID, "unknown job template");
+    if (j->dtype != HIPMR_F32 && j->dtype != HIPMR_BF16)
+        return fail(HIPMR_E_UNSUPPORTED, "serving jobs take float or bfloat16 arrays");
+    if (j->n < 0) return fail(HIPMR_E_INVALID, "n must be >= 0");
+    if (!j->out) return fail(HIPMR_E_INVALID, "out is NULL");
+    if (j->n > 0 && (!j->x || (needs_y(j->tmpl) && !j->y) || (needs_w(j->tmpl) && !j->w)))
+        return fail(HIPMR_E_INVALID, "an input array of the job's template is NULL");
+    if (job_bytes(*j) > s->cfg.hbm_budget_bytes)
+        return fail(HIPMR_E_BUDGET, "the job alone exceeds the memory budget");
+    if (job_tiles(*j, job_head(*j)) > s->cfg.max_batch_tiles)
+        return fail(HIPMR_E_BUDGET, "the job has more tiles than max_batch_tiles");
+    return HIPMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t hipmr_server_now_ns(void) { return now_ns(); }
+
+size_t hipmr_server_workspace_bytes(const hipmr_server_config* in) {
+    hipmr_server_config c = resolved(in);
+    return (size_t)c.nstreams * slot_bytes(c);
+}
+
+hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace, size_t workspace_bytes,
+                                 hipmr_server_t* out) {
+    clear_error();
+    if (!out) return fail(HIPMR_E_INVALID, "NULL argument");
+    *out = nullptr;
+    hipmr_server_config c = resolved(in);
+    if (c.nstreams < 1 || c.nstreams > 16) return fail(HIPMR_E_INVALID, "nstreams must be in [1, 16]");
+    if (c.max_batch_jobs < 1 || c.max_batch_jobs > kMaxBatchJobs)
+        return fail(HIPMR_E_INVALID, "max_batch_jobs must be in [1, 4096]");
+    if (c.max_batch_tiles < 1 || c.blocks_per_cu < 1) return fail(HIPMR_E_INVALID, "bad batch limits");
+    if (!workspace || workspace_bytes < hipmr_server_workspace_bytes(&c))
+        return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_server_workspace_bytes()");
+    auto s = std::make_unique<hipmr_server>();
+    s->cfg = c;
+    if (hipGetDevice(&s->device) != hipSuccess) return fail(HIPMR_E_HIP, "hipGetDevice failed");
+    s->cus = device_cu_count();
+    // compile the serving kernels (templates x dtypes) through the RTC cache
+    s->prefix = "hipmr_serve";
+    hipmr_status st;
+    s->co = get_or_build(serve_source(s->prefix), s->prefix + "_s1", &st);
+    if (!s->co) return st;
+    const std::string& image = code_object_image(*s->co);
+    hipError_t e = hipModuleLoadData(&s->module, image.data());
+    if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+    struct { hipFunction_t* f; const char* suffix; } fns[] = {
+        {&s->f_s1, "_s1"}, {&s->f_s2, "_s2"}, {&s->f_one1, "_one1"}, {&s->f_one2, "_one2"}};
+    for (auto& f : fns) {
+        e = hipModuleGetFunction(f.f, s->module, (s->prefix + f.suffix).c_str());
+        if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+    }
+    s->slots.resize(c.nstreams);
+    char* base = (char*)workspace;
+    for (int k = 0; k < c.nstreams; ++k) {
+        auto& sl = s->slots[k];
+        // default-priority, non-blocking streams
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&sl.host_desc, (size_t)c.max_batch_jobs * sizeof(DevJob),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(HIPMR_E_HIP, "creating the serving streams, events or pinned buffers failed");
+        sl.dev_desc = (DevJob*)(base + (size_t)k * slot_bytes(c));
+        sl.tpart = base + (size_t)k * slot_bytes(c) + align256((size_t)c.max_batch_jobs * sizeof(DevJob));
+    }
+    hipmr_server* raw = s.get();
+    s->worker = std::thread([raw] { raw->loop(); });
+    *out = s.release();
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_server_submit(hipmr_server_t s, const hipmr_sjob* job, uint64_t* ticket) {
+    clear_error();
+    if (!s) return fail(HIPMR_E_INVALID, "NULL server");
+    hipmr_status st = validate_job(s, job);
+    if (st != HIPMR_OK) return st;
+    hipmr_server::Pending p{*job, 0, now_ns(), job_bytes(*job), 0, job_head(*job)};
+    p.tiles = job_tiles(*job, p.head);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        p.ticket = s->next_ticket++;
+        s->incoming.push_back(p);
+        ++s->unfinished;
+    }
+    s->cv_work.notify_one();
+    if (ticket) *ticket = p.ticket;
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_server_poll(hipmr_server_t s, hipmr_completion* done, int32_t cap, int32_t* ndone) {
+    clear_error();
+    if (!s || !ndone || (cap > 0 && !done)) return fail(HIPMR_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t k = 0;
+    while (k < cap && !s->finished.empty()) {
+        done[k++] = s->finished.front();
+        s->finished.erase(s->finished.begin());
+    }
+    *ndone = k;
+    if (s->worker_status != HIPMR_OK) return fail(s->worker_status, s->worker_error);
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_server_wait_idle(hipmr_server_t s) {
+    clear_error();
+    if (!s) return fail(HIPMR_E_INVALID, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->unfinished == 0; });
+    return HIPMR_OK;
+}
+
+hipmr_status hipmr_server_run_schedule(hipmr_server_t s, const hipmr_sjob* jobs, int32_t njobs,
+                                       hipmr_completion* done) {
+    clear_error();
+    if (!s || (njobs > 0 && (!jobs || !done)) || njobs < 0) return fail(HIPMR_E_INVALID, "NULL argument");
+    int32_t valid = 0;
+    for (int32_t k = 0; k < njobs; ++k) {
+        if (k > 0 && jobs[k].arrival_ns < jobs[k - 1].arrival_ns)
+            return fail(HIPMR_E_INVALID, "arrival times must be non-decreasing");
+    }
+    std::vector<hipmr_sjob> copy(jobs, jobs + njobs);
+    std::vector<char> ok(njobs, 1);
+    for (int32_t k = 0; k < njobs; ++k) {
+        hipmr_status st = validate_job(s, &copy[k]);
+        if (st != HIPMR_OK) {
+            // rejected at admission: reported, never packed
+            done[k] = hipmr_completion{(1ull << 62) + (uint64_t)k, st, 0, 0, 0, 0};
+            ok[k] = 0;
+            copy[k].n = 0;
+            copy[k].tmpl = -1;
+        } else {
+            ++valid;
+        }
+    }
+    std::vector<hipmr_sjob> sched;
+    std::vector<int32_t> index;
+    for (int32_t k = 0; k < njobs; ++k)
+        if (ok[k]) {
+            sched.push_back(copy[k]);
+            index.push_back(k);
+        }
+    std::vector<hipmr_completion> out(sched.size());
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->sched) return fail(HIPMR_E_INVALID, "a schedule is already running on this server");
+        s->sched = sched.data();
+        s->sched_n = (int32_t)sched.size();
+        s->sched_next = 0;
+        s->sched_done = 0;
+        s->sched_out = out.data();
+        s->unfinished += (int64_t)sched.size();
+        s->sched_t0 = now_ns();
+    }
+    s->cv_work.notify_one();
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] { return s->sched_done == s->sched_n; });
+        s->sched = nullptr;
+        s->sched_out = nullptr;
+    }
+    for (size_t k = 0; k < sched.size(); ++k) {
+        done[index[k]] = out[k];
+        done[index[k]].ticket = (uint64_t)index[k];
+        done[index[k]].arrival_ns -= s->sched_t0;
+        done[index[k]].launch_ns -= s->sched_t0;
+        done[index[k]].done_ns -= s->sched_t0;
+    }
+    for (int32_t k = 0; k < njobs; ++k)
+        if (!ok[k]) done[k].ticket = (uint64_t)k;
+    if (s->worker_status != HIPMR_OK) return fail(s->worker_status, s->worker_error);
+    return HIPMR_OK;
+}
+
+void hipmr_server_destroy(hipmr_server_t s) {
+    if (!s) return;
+    s->stop = true;
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    for (auto& sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.host_desc) (void)hipHostFree(sl.host_desc);
+    }
+    if (s->module) (void)hipModuleUnload(s->module);
+    delete s;
+}
+
+}  // extern "C"

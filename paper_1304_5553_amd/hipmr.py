@@ -120,6 +120,14 @@ _SIGS = {
                                         ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_autotune_reduce": (_I32, [_VP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ, _I32,
                                      ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_server_workspace_bytes": (_SZ, [_VP]),
+    "hipmr_server_create": (_I32, [_VP, _VP, _SZ, ctypes.POINTER(_VP)]),
+    "hipmr_server_submit": (_I32, [_VP, _VP, ctypes.POINTER(ctypes.c_uint64)]),
+    "hipmr_server_poll": (_I32, [_VP, _VP, _I32, ctypes.POINTER(_I32)]),
+    "hipmr_server_wait_idle": (_I32, [_VP]),
+    "hipmr_server_run_schedule": (_I32, [_VP, _VP, _I32, _VP]),
+    "hipmr_server_destroy": (None, [_VP]),
+    "hipmr_server_now_ns": (_I64, []),
     "hipmr_graph_begin_capture": (_I32, [_VP]),
     "hipmr_graph_end_capture": (_I32, [_VP, ctypes.POINTER(_VP)]),
     "hipmr_graph_launch": (_I32, [_VP, _VP]),
@@ -556,3 +564,93 @@ class ReductionKernel:
             out = torch.empty((), dtype=torch_dtype(self.kernel.result_dtype), device=device)
         return reduce(self.kernel, self.map_expr, self.reduce_expr, self.neutral, n, args, out,
                       stream=stream, config=config)
+
+
+# --------------------------------------------------------------- serving
+JOB_SUM, JOB_DOT, JOB_NORM2, JOB_MAX, JOB_AXPBY_SUM, JOB_COUNT_POS, JOB_SUMSQ, JOB_WMEAN = range(8)
+JOB_NAMES = ["sum", "dot", "norm2", "max", "axpby_sum", "count_pos", "sumsq", "wmean"]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("nstreams", ctypes.c_int32),
+                ("max_batch_jobs", ctypes.c_int32), ("max_batch_tiles", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+def _sjob_dtype():
+    import numpy as np
+    dt = np.dtype([("x", np.uint64), ("y", np.uint64), ("w", np.uint64), ("n", np.int64),
+                   ("tmpl", np.int32), ("dtype", np.int32), ("arrival_ns", np.int64),
+                   ("out", np.uint64), ("a", np.float32), ("b", np.float32)])
+    assert dt.itemsize == 64
+    return dt
+
+
+def _completion_dtype():
+    import numpy as np
+    dt = np.dtype([("ticket", np.uint64), ("status", np.int32), ("batch_jobs", np.int32),
+                   ("arrival_ns", np.int64), ("launch_ns", np.int64), ("done_ns", np.int64)])
+    assert dt.itemsize == 40
+    return dt
+
+
+class Server:
+    """The serving request loop (hipmr_server_*): jobs are numpy records of
+    ``Server.JOB`` (device pointers as integers)."""
+
+    def __init__(self, hbm_budget_bytes=0, nstreams=0, max_batch_jobs=0, max_batch_tiles=0,
+                 blocks_per_cu=0, device=None):
+        import torch
+        self.JOB = _sjob_dtype()
+        self.COMPLETION = _completion_dtype()
+        self.cfg = ServerConfig(hbm_budget_bytes, nstreams, max_batch_jobs, max_batch_tiles,
+                                blocks_per_cu)
+        nbytes = lib().hipmr_server_workspace_bytes(ctypes.byref(self.cfg))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8,
+                                     device=device or torch.device("cuda"))
+        h = _VP()
+        _check(lib().hipmr_server_create(ctypes.byref(self.cfg),
+                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                         ctypes.byref(h)))
+        self._s = h
+
+    def jobs(self, count):
+        import numpy as np
+        return np.zeros(count, dtype=self.JOB)
+
+    def submit(self, job):
+        import numpy as np
+        rec = np.ascontiguousarray(np.asarray(job, dtype=self.JOB).reshape(1))
+        t = ctypes.c_uint64()
+        _check(lib().hipmr_server_submit(self._s, rec.ctypes.data, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, cap=4096):
+        import numpy as np
+        out = np.zeros(cap, dtype=self.COMPLETION)
+        nd = _I32()
+        _check(lib().hipmr_server_poll(self._s, out.ctypes.data, cap, ctypes.byref(nd)))
+        return out[:nd.value]
+
+    def wait_idle(self):
+        _check(lib().hipmr_server_wait_idle(self._s))
+
+    def run_schedule(self, jobs):
+        import numpy as np
+        jobs = np.ascontiguousarray(jobs, dtype=self.JOB)
+        done = np.zeros(len(jobs), dtype=self.COMPLETION)
+        _check(lib().hipmr_server_run_schedule(self._s, jobs.ctypes.data, len(jobs),
+                                               done.ctypes.data))
+        return done
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value and _lib is not None:
+            _lib.hipmr_server_destroy(self._s)
+        self._s = None
+
+    def __del__(self):
+        self.close()
+
+
+def server_now_ns():
+    return lib().hipmr_server_now_ns()

@@ -19,6 +19,10 @@ Workloads (the paper publishes no data sets; its listings use small random or
 * ``segments``: 4096 segment lengths lognormal with median 2**12 and sigma
   sqrt(2 ln 4) (so the mean is 2**14), rounded and clipped to [1, 2**20]
   (seed 4), total 62,032,791; x, y float32 ~ U[-1, 1] drawn after the lengths.
+* ``serving``: a resident pool of 2**24 x, y ~ U[-1, 1] and w ~ U[0, 1)
+  (float32 and bfloat16, seed 5) and a Poisson schedule per rate (seed
+  [5, rate]): sizes floor(2^U), U ~ U[10, 24], one of 8 templates uniformly,
+  float32 or bfloat16 with probability 1/2, a random offset into the pool.
 """
 
 from __future__ import annotations
@@ -133,3 +137,38 @@ def segments(nseg=N_SEGMENTS, median=4096.0, sigma=SEGMENT_SIGMA, max_len=1 << 2
     x = uniform_f32(rng, total)
     y = uniform_f32(rng, total)
     return offsets, x, y
+
+
+# -------------------------------------------------------------- serving
+N_POOL = 1 << 24
+SERVING_RATES = (2000, 10000, 50000)
+
+
+def serving_pool(n=N_POOL, seed=5):
+    """Device-resident input pool: x, y ~ U[-1, 1], w ~ U[0, 1), float32 and
+    their bfloat16 roundings (torch's CPU conversion, round to nearest even)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    f32 = {"x": uniform_f32(rng, n), "y": uniform_f32(rng, n),
+           "w": rng.uniform(0.0, 1.0, n).astype(np.float32)}
+    bf16 = {k: torch.from_numpy(v).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+            for k, v in f32.items()}
+    return f32, bf16
+
+
+def serving_schedule(rate, duration_s, seed=5, pool_n=N_POOL, log2_min=10, log2_max=24):
+    """Poisson arrivals at `rate` jobs/s for `duration_s`; per job: n = floor(2^U),
+    U ~ U[log2_min, log2_max]; template uniform over the 8; dtype float32 or
+    bfloat16 with probability 1/2; a random offset into the pool."""
+    rng = np.random.default_rng([seed, int(rate)])
+    count = int(rate * duration_s * 1.2) + 16
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    arrivals = arrivals[arrivals < duration_s]
+    m = arrivals.size
+    n = np.floor(2.0 ** rng.uniform(log2_min, log2_max, m)).astype(np.int64)
+    n = np.minimum(n, pool_n)
+    tmpl = rng.integers(0, 8, m).astype(np.int32)
+    bf16 = rng.random(m) < 0.5
+    offset = (rng.random(m) * (pool_n - n + 1)).astype(np.int64)
+    return {"arrival_ns": (arrivals * 1e9).astype(np.int64), "n": n, "tmpl": tmpl,
+            "bf16": bf16, "offset": offset}
