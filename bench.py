@@ -209,6 +209,65 @@ def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
     return res
 
 
+def bench_serving(torch, hm, workloads, dev, duration_s=2.0, warmup_s=0.5):
+    """Poisson streams at 2k, 10k and 50k jobs/s (8 templates, float32 /
+    bfloat16 50/50, n log-uniform over [2^10, 2^24], slices of a resident 2^24
+    pool), replayed open-loop through the continuous-batching loop and
+    through the one-launch-pair-per-job baseline on the same 4 streams;
+    latency = scheduled arrival -> result visible on the host."""
+    f32, bf16 = workloads.serving_pool()
+    dev_f32 = {k: torch.from_numpy(v).to(dev) for k, v in f32.items()}
+    dev_bf16 = {k: torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).to(dev)
+                for k, v in bf16.items()}
+    res = {"pool": workloads.N_POOL, "duration_s": duration_s, "warmup_s": warmup_s,
+           "budget_bytes": 64 << 30, "nstreams": 4, "rates": {}}
+    for rate in workloads.SERVING_RATES:
+        sched = workloads.serving_schedule(rate, warmup_s + duration_s)
+        m = len(sched["n"])
+        es = np.where(sched["bf16"], 2, 4)
+        arrays = np.where(np.isin(sched["tmpl"], [1, 4, 7]), 2, 1)
+        job_bytes = sched["n"] * es * arrays
+        out = torch.empty(m, dtype=torch.float64, device=dev)
+        row = {"jobs": int(m)}
+        for mode, max_jobs in (("batched", 1024), ("per_job", 1)):
+            server = hm.Server(hbm_budget_bytes=64 << 30, nstreams=4, max_batch_jobs=max_jobs)
+            jobs = server.jobs(m)
+            for key, src in (("x", None), ("y", None), ("w", None)):
+                base_f = dev_f32[key].data_ptr()
+                base_b = dev_bf16[key].data_ptr()
+                jobs[key] = np.where(sched["bf16"], base_b + sched["offset"] * 2,
+                                     base_f + sched["offset"] * 4).astype(np.uint64)
+            jobs["n"] = sched["n"]
+            jobs["tmpl"] = sched["tmpl"]
+            jobs["dtype"] = np.where(sched["bf16"], hm.hipmr.BF16, hm.hipmr.F32)
+            jobs["arrival_ns"] = sched["arrival_ns"]
+            jobs["out"] = out.data_ptr() + 8 * np.arange(m, dtype=np.uint64)
+            jobs["a"], jobs["b"] = 2.5, -0.5
+            done = server.run_schedule(jobs)
+            server.close()
+            meas = sched["arrival_ns"] >= int(warmup_s * 1e9)
+            lat = (done["done_ns"] - done["arrival_ns"])[meas] / 1e3
+            first = int(np.min(done["arrival_ns"][meas]))
+            last = int(np.max(done["done_ns"][meas]))
+            span = (last - first) / 1e9
+            queue = (done["launch_ns"] - done["arrival_ns"])[meas] / 1e3
+            service = (done["done_ns"] - done["launch_ns"])[meas] / 1e3
+            row[mode] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                         "p99_us": round(float(np.percentile(lat, 99)), 1),
+                         "mean_us": round(float(np.mean(lat)), 1),
+                         "jobs_per_s": round(int(meas.sum()) / span, 1),
+                         "GB/s": round(float(job_bytes[meas].sum()) / span / 1e9, 2),
+                         "queue_p50_us": round(float(np.percentile(queue, 50)), 1),
+                         "service_p50_us": round(float(np.percentile(service, 50)), 1),
+                         "mean_batch_jobs": round(float(np.mean(done["batch_jobs"][meas])), 2),
+                         "status_ok": bool(np.all(done["status"] == 0))}
+        row["p99_speedup"] = round(row["per_job"]["p99_us"] / row["batched"]["p99_us"], 2)
+        row["p50_speedup"] = round(row["per_job"]["p50_us"] / row["batched"]["p50_us"], 2)
+        res["rates"][str(rate)] = row
+        print(f"serving {rate}/s done", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -269,8 +328,11 @@ def main():
             hm.reduce(kk["R3"], workloads.R_MAX[1], "max(a,b)", "-INFINITY", n, [xd],
                       outs["max"], ws)
 
+    last = {}
+
     def step(events=None):
         kk = kernels()
+        last.update(kk)
         for name in ops:
             if events is not None:
                 events[name][0].record(stream)
@@ -311,7 +373,7 @@ def main():
     dominant = max(ops, key=lambda o: np.mean(per_op_ms[o]))
     dom_ms = float(np.mean(per_op_ms[dominant]))
     achieved = bytes_per[dominant] / (dom_ms / 1e3) / 1e9
-    dom_symbol = ks[dominant].last_symbols()[0]
+    dom_symbol = last[dominant].last_symbols()[0]
     traffic = counter_traffic(dom_symbol)
 
     # results of the last step (sanity: exact integer results are printed)
@@ -358,6 +420,7 @@ def main():
         print("precision done", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(torch, hm, workloads, dev)
         print("batched done", file=sys.stderr, flush=True)
+        line["served"] = bench_serving(torch, hm, workloads, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, k, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -40,6 +40,7 @@ namespace {
 
 constexpr int kServeBlock = 256;
 constexpr int kMaxBatchJobs = 4096;      // LDS table of job tile offsets
+constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
 // hipmr_sjob struct in the kernels below).
@@ -56,6 +57,11 @@ struct DevJob {
     float a, b;
 };
 static_assert(sizeof(DevJob) == 64, "job descriptor layout");
+
+struct InlineJobs {
+    int njobs, total_tiles, pad0, pad1;
+    DevJob jobs[kInlineJobs];
+};
 
 const char* kServeKernels = R"HIP(
 struct hipmr_sjob {
@@ -254,6 +260,37 @@ extern "C" __global__ void __launch_bounds__(256)
   hipmr_job_finish(J, J.tile0, t1, tpart, threadIdx.x & 63);
 }
 
+// Small batches: the descriptors travel by value in the kernel arguments
+// (no separate host-to-device copy before the launch).
+struct hipmr_jobs_inline {
+  int njobs, total_tiles, pad0, pad1;
+  hipmr_sjob jobs[@@NINLINE@@];
+};
+
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_i1(const hipmr_jobs_inline B, float2* __restrict__ tpart)
+{
+  const int lane = threadIdx.x & 63;
+  const int nwaves = gridDim.x * 4;
+  for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < B.total_tiles; t += nwaves) {
+    int j = 0;                                  // the last job with tile0 <= t
+    for (int k = 1; k < B.njobs; ++k) j = B.jobs[k].tile0 <= t ? k : j;
+    const hipmr_sjob J = B.jobs[j];
+    const float2 r = hipmr_job_dispatch(J, t - J.tile0, lane);
+    if (lane == 0) tpart[t] = r;
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_i2(const hipmr_jobs_inline B, const float2* __restrict__ tpart)
+{
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= B.njobs) return;
+  const hipmr_sjob J = B.jobs[j];
+  const int t1 = j + 1 < B.njobs ? B.jobs[j + 1].tile0 : B.total_tiles;
+  hipmr_job_finish(J, J.tile0, t1, tpart, threadIdx.x & 63);
+}
+
 // One job, descriptor by value: the one-launch-pair-per-job path.
 extern "C" __global__ void __launch_bounds__(256)
 @@PREFIX@@_one1(hipmr_sjob J, float2* __restrict__ tpart)
@@ -348,6 +385,7 @@ std::string serve_source(const std::string& prefix) {
     rep("@@PREFIX@@", prefix);
     rep("@@MAXJ@@", std::to_string(kMaxBatchJobs));
     rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
+    rep("@@NINLINE@@", std::to_string(kInlineJobs));
     return src;
 }
 
@@ -359,6 +397,7 @@ struct hipmr_server {
     std::shared_ptr<CodeObject> co;
     hipModule_t module = nullptr;
     hipFunction_t f_s1 = nullptr, f_s2 = nullptr, f_one1 = nullptr, f_one2 = nullptr;
+    hipFunction_t f_i1 = nullptr, f_i2 = nullptr;
     std::string prefix;
     int cus = 256;
 
@@ -434,6 +473,24 @@ struct hipmr_server {
                 void* a2[2] = {&d, &s.tpart};
                 e = hipModuleLaunchKernel(f_one2, 1, 1, 1, 64, 1, 1, 0, s.stream, a2, nullptr);
             }
+            if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
+        } else if (nj <= kInlineJobs) {
+            InlineJobs b{};
+            int tile0 = 0;
+            for (int k = 0; k < nj; ++k) {
+                const Pending& p = s.jobs[k];
+                b.jobs[k] = DevJob{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype,
+                                   tile0, p.head, p.job.out, p.job.a, p.job.b};
+                tile0 += p.tiles;
+            }
+            b.njobs = nj;
+            b.total_tiles = tile0;
+            int grid = std::max(1, std::min(cfg.blocks_per_cu * cus, (tile0 + 3) / 4));
+            void* a1[2] = {&b, &s.tpart};
+            hipError_t e = hipModuleLaunchKernel(f_i1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
+            void* a2[2] = {&b, &s.tpart};
+            if (e == hipSuccess)
+                e = hipModuleLaunchKernel(f_i2, (nj + 3) / 4, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         } else {
             int tile0 = 0;
@@ -611,7 +668,8 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
     hipError_t e = hipModuleLoadData(&s->module, image.data());
     if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
     struct { hipFunction_t* f; const char* suffix; } fns[] = {
-        {&s->f_s1, "_s1"}, {&s->f_s2, "_s2"}, {&s->f_one1, "_one1"}, {&s->f_one2, "_one2"}};
+        {&s->f_s1, "_s1"}, {&s->f_s2, "_s2"}, {&s->f_one1, "_one1"}, {&s->f_one2, "_one2"},
+        {&s->f_i1, "_i1"}, {&s->f_i2, "_i2"}};
     for (auto& f : fns) {
         e = hipModuleGetFunction(f.f, s->module, (s->prefix + f.suffix).c_str());
         if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));

@@ -170,3 +170,22 @@ def test_submit_and_poll(dev, pool):
     got = out.cpu().numpy()
     for k in range(0, len(jobs), 5):
         oracle_check(k, float(got[k]), sched, pool)
+
+
+@pytest.mark.parametrize("max_jobs", [24, 1024])
+def test_burst_packs_large_batches(dev, pool, max_jobs):
+    # every job arrives at once on one stream: batches fill up to the cap,
+    # which covers both the by-value descriptor path (up to 24 jobs) and the
+    # device descriptor table (more)
+    sched = workloads.serving_schedule(50000, 0.006, pool_n=POOL_N, log2_max=14)
+    sched["arrival_ns"][:] = 0
+    out = torch.full((len(sched["n"]),), float("nan"), dtype=torch.float64, device=dev)
+    server = hm.Server(nstreams=1, max_batch_jobs=max_jobs)
+    done = server.run_schedule(make_jobs(server, sched, pool, out))
+    torch.cuda.synchronize()
+    server.close()
+    assert len(sched["n"]) > 200 and np.all(done["status"] == 0)
+    assert int(np.max(done["batch_jobs"])) == min(max_jobs, len(sched["n"]))
+    got = out.cpu().numpy()
+    for k in range(len(got)):
+        oracle_check(k, float(got[k]), sched, pool)
