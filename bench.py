@@ -41,7 +41,11 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 28)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
-                   help="skip the precision and batching measurements")
+                   help="skip the precision, batching and serving measurements")
+    p.add_argument("--extensions", default="precision,batched,served",
+                   help="comma list of the extension measurements to run")
+    p.add_argument("--serving-duration", type=float, default=2.0,
+                   help="measured seconds of each serving rate (after 0.5 s of warm-up)")
     p.add_argument("--cpu-sample", type=int, default=1 << 27,
                    help="elements per op for the oracle timing")
     p.add_argument("--ops", default="E1,E2,R1,R2,R3",
@@ -132,12 +136,13 @@ def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
             return bufs[it[0] % copies]
         inv = 1.0 / q.scale
         t_sum = _time_ms(torch, lambda: hm.reduce_compensated(k, n, [nxt()], inv, o, ws), reps, stream)
+        sum_symbols = k.last_symbols()
         t_nrm = _time_ms(torch, lambda: hm.norm2(k, n, [nxt()], inv, 2, o, ws), reps, stream)
         nbytes = n * host.element_size()
         out[fmt] = {"sum_ms": round(t_sum, 4), "sum_GB/s": round(nbytes / t_sum / 1e6, 1),
                     "norm2_ms": round(t_nrm, 4),
                     "norm2_GB/s": round(2 * nbytes / t_nrm / 1e6, 1),
-                    "sum_symbols": k.last_symbols()}
+                    "sum_symbols": sum_symbols, "norm2_symbols": k.last_symbols()}
         del bufs
         torch.cuda.empty_cache()
     return {"n": n, "workload": "lognormal(0,3) x random sign, per-tensor power-of-two scale",
@@ -413,14 +418,18 @@ def main():
         "results": result,
         "wall_s_timed": round(wall, 3),
     }
-    if not args.no_extensions:
+    ext = set() if args.no_extensions else {e.strip() for e in args.extensions.split(",")}
+    if ext:
         del xd, yd, kd, z
         torch.cuda.empty_cache()
+    if "precision" in ext:
         line["precision"] = bench_precision(torch, hm, workloads, dev, stream)
         print("precision done", file=sys.stderr, flush=True)
+    if "batched" in ext:
         line["batched"] = bench_batched(torch, hm, workloads, dev)
         print("batched done", file=sys.stderr, flush=True)
-        line["served"] = bench_serving(torch, hm, workloads, dev)
+    if "served" in ext:
+        line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, k, args.cpu_sample)
     print(json.dumps(line), flush=True)
