@@ -697,16 +697,21 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 // there) and T = 64 * V * IPT.  One wave reduces one tile.  The partition of
 // a segment depends only on its bounds, V and IPT, never on other segments.
 const char* kSegHelpers = R"HIP(
-__device__ __forceinline__ void hipmr_seg_bounds(const long long* __restrict__ off, int s,
-                                                 long long total, long long head, int V,
-                                                 long long& a, long long& b, long long& ab) {
-  a = off[s];
-  b = off[s + 1];
+__device__ __forceinline__ void hipmr_seg_clamp(long long a0, long long b0, long long total,
+                                                long long head, int V,
+                                                long long& a, long long& b, long long& ab) {
+  a = a0;
+  b = b0;
   a = a < 0 ? 0 : (a > total ? total : a);
   b = b < a ? a : (b > total ? total : b);
   long long r = (head - a) % V;
   if (r < 0) r += V;
   ab = a + r < b ? a + r : b;
+}
+__device__ __forceinline__ void hipmr_seg_bounds(const long long* __restrict__ off, int s,
+                                                 long long total, long long head, int V,
+                                                 long long& a, long long& b, long long& ab) {
+  hipmr_seg_clamp(off[s], off[s + 1], total, head, V, a, b, ab);
 }
 __device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long long ab, long long T) {
   if (b == a) return 0;
@@ -715,28 +720,38 @@ __device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long lo
 }
 )HIP";
 
-// Planner: tiles per segment and their exclusive prefix, one block.
+// Planner: tiles per segment and their exclusive prefix, one block.  Each
+// thread takes 4 consecutive segments per round of 4096 (all offset loads
+// issued before any is used).
 const char* kSegPlan = R"HIP(
 extern "C" __global__ void __launch_bounds__(1024)
 @@KNAME@@(const long long* __restrict__ hipmr_off, int hipmr_nseg, long long hipmr_total,
           long long hipmr_head, int* __restrict__ hipmr_tile_start)
 {
-  constexpr int B = 1024, V = @@VEC@@;
+  constexpr int B = 1024, R = 4, V = @@VEC@@;
   constexpr long long T = 64LL * @@VEC@@ * @@IPT@@;
   __shared__ int hipmr_wsum[B / 64];
   __shared__ int hipmr_carry;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (threadIdx.x == 0) hipmr_carry = 0;
   __syncthreads();
-  for (int base = 0; base < hipmr_nseg; base += B) {
-    const int s = base + threadIdx.x;
-    int tiles = 0;
-    if (s < hipmr_nseg) {
-      long long a, b, ab;
-      hipmr_seg_bounds(hipmr_off, s, hipmr_total, hipmr_head, V, a, b, ab);
-      tiles = hipmr_seg_tiles(a, b, ab, T);
+  for (int base = 0; base < hipmr_nseg; base += B * R) {
+    const int s0 = base + threadIdx.x * R;
+    long long o[R + 1];
+#pragma unroll
+    for (int j = 0; j <= R; ++j) o[j] = s0 + j <= hipmr_nseg ? hipmr_off[s0 + j] : 0;
+    int t[R], tsum = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      t[j] = 0;
+      if (s0 + j < hipmr_nseg) {
+        long long a, b, ab;
+        hipmr_seg_clamp(o[j], o[j + 1], hipmr_total, hipmr_head, V, a, b, ab);
+        t[j] = hipmr_seg_tiles(a, b, ab, T);
+      }
+      tsum += t[j];
     }
-    int x = tiles;                               // inclusive scan in the wave
+    int x = tsum;                                // inclusive scan in the wave
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int y = __shfl_up(x, d, 64);
@@ -754,10 +769,15 @@ extern "C" __global__ void __launch_bounds__(1024)
       if (l < B / 64) hipmr_wsum[l] = v;
     }
     __syncthreads();
-    const int excl = hipmr_carry + (w > 0 ? hipmr_wsum[w - 1] : 0) + x - tiles;
-    if (s < hipmr_nseg) hipmr_tile_start[s] = excl;
+    const int excl = hipmr_carry + (w > 0 ? hipmr_wsum[w - 1] : 0) + x - tsum;
+    int run = excl;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (s0 + j < hipmr_nseg) hipmr_tile_start[s0 + j] = run;
+      run += t[j];
+    }
     __syncthreads();
-    if (threadIdx.x == B - 1) hipmr_carry = excl + tiles;
+    if (threadIdx.x == B - 1) hipmr_carry = excl + tsum;
     __syncthreads();
   }
   if (threadIdx.x == 0) hipmr_tile_start[hipmr_nseg] = hipmr_carry;
@@ -864,7 +884,16 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   hipmr_acc r = hipmr_neutral;
   const int t1 = hipmr_tile_start[s + 1];
-  for (int t = hipmr_tile_start[s] + lane; t < t1; t += 64) r = hipmr_combine(r, hipmr_tpart[t]);
+  // lane order t, t + 64, t + 128, ...; eight loads in flight per round
+  for (int t = hipmr_tile_start[s] + lane; t < t1; t += 64 * 8) {
+    hipmr_acc v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (t + 64 * k < t1) v[k] = hipmr_tpart[t + 64 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (t + 64 * k < t1) r = hipmr_combine(r, v[k]);
+  }
   r = hipmr_block_reduce<64>(r, hipmr_neutral);
   if (lane == 0) hipmr_out[s] = r;
 }

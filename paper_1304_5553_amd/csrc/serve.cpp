@@ -14,13 +14,16 @@
 //   - a batch is two launches of run-time compiled kernels:
 //       1. a persistent kernel whose waves take fixed-size tiles of any job in
 //          the batch (a wave-uniform switch over template x dtype);
-//       2. one wave per job folding that job's tile partials in order and
-//          finishing the job (sqrt, ratio);
-//   - completion is observed through an event per batch.
-// A job's tiles depend only on the job (its length, dtype and alignment), so
-// its result is bitwise the same alone or in any mix.  With max_batch_jobs
-// = 1 the loop issues one launch pair per job with the descriptor passed by
-// value: the baseline.
+//       2. one block per job folding that job's tile partials in a fixed
+//          order and finishing the job (sqrt, ratio);
+//   - completion is observed through per-job flags in mapped host memory,
+//     written by the finishing block after the result (an event per batch
+//     serves as a watchdog for errors).
+// A job's tiles depend only on the job (its length, dtype and alignment; big
+// jobs get longer tiles so that none has more than 2048), so its result is
+// bitwise the same alone or in any mix.  A batch of one job passes its
+// descriptor by value; with max_batch_jobs = 1 every job runs that way, one
+// launch pair per job: the baseline.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -41,6 +44,7 @@ namespace {
 constexpr int kServeBlock = 256;
 constexpr int kMaxBatchJobs = 4096;      // LDS table of job tile offsets
 constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
+constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, ask the event
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
 // hipmr_sjob struct in the kernels below).
@@ -72,18 +76,16 @@ struct hipmr_sjob {
   float a, b;
 };
 
-// One element's contribution of template TMPL to the accumulators (s0, s1).
+// One element's terms (t0, t1) under template TMPL; t1 is the weight of the
+// weighted mean and 0 otherwise.
 template <int TMPL>
-__device__ __forceinline__ void hipmr_job_elem(float& s0, float& s1, float x, float y, float w,
-                                               float a, float b) {
-  if constexpr (TMPL == 0) s0 += x;                                   // sum
-  else if constexpr (TMPL == 1) s0 += x * y;                          // dot
-  else if constexpr (TMPL == 2) s0 += x * x;                          // L2 norm (sqrt at the end)
-  else if constexpr (TMPL == 3) s0 = __builtin_elementwise_maximum(s0, x);   // max
-  else if constexpr (TMPL == 4) s0 += a * x + b * y;                  // axpby, then sum
-  else if constexpr (TMPL == 5) s0 += x > 0.0f ? 1.0f : 0.0f;         // count(x > 0)
-  else if constexpr (TMPL == 6) s0 += x * x;                          // sum of squares
-  else { s0 += w * x; s1 += w; }                                      // weighted mean
+__device__ __forceinline__ float2 hipmr_job_term(float x, float y, float w, float a, float b) {
+  if constexpr (TMPL == 0 || TMPL == 3) return make_float2(x, 0.0f);  // sum, max
+  else if constexpr (TMPL == 1) return make_float2(x * y, 0.0f);      // dot
+  else if constexpr (TMPL == 2 || TMPL == 6) return make_float2(x * x, 0.0f);  // norm, sum of squares
+  else if constexpr (TMPL == 4) return make_float2(a * x + b * y, 0.0f);       // axpby, then sum
+  else if constexpr (TMPL == 5) return make_float2(x > 0.0f ? 1.0f : 0.0f, 0.0f);  // count(x > 0)
+  else return make_float2(w * x, w);                                  // weighted mean
 }
 
 template <int TMPL>
@@ -92,113 +94,149 @@ __device__ __forceinline__ float hipmr_job_comb(float a, float b) {
   else return a + b;
 }
 
-// Tile k of job J: tile 0 holds the unaligned head and up to TT aligned
-// elements, later tiles TT elements; lanes keep U chunks of V elements.
-template <int TMPL, typename T, int V, int U>
+template <int TMPL>
+__device__ __forceinline__ float2 hipmr_job_comb2(float2 a, float2 b) {
+  return make_float2(hipmr_job_comb<TMPL>(a.x, b.x), a.y + b.y);
+}
+
+// Tile geometry of a job, a function of the job alone: `ab` unaligned head
+// elements (all arrays 16-byte aligned after them; 0 when they share no
+// alignment), then tiles of `tt` elements = P passes of 64 lanes x 4 chunks x
+// V elements.  P (1, 2, 4 or 8) is the smallest that keeps the job at or
+// under 2048 tiles; arrays without a common alignment use P = 1.
+struct hipmr_geom { long long ab, tt; int passes, tiles; };
+
+__device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
+  const long long tt0 = J.dtype == @@BF16CODE@@ ? 64 * 8 * 4 : 64 * 4 * 4;
+  hipmr_geom g;
+  g.ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
+  const long long body = J.n - g.ab;
+  int p = 1;
+  while (J.head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 2048) p *= 2;
+  g.passes = p;
+  g.tt = tt0 * p;
+  const long long t = (body + g.tt - 1) / g.tt;
+  g.tiles = J.n <= 0 ? 0 : (t < 1 ? 1 : (int)t);
+  return g;
+}
+
+// Tile k of job J, reduced by one wave.  Tile 0 also holds the unaligned
+// head.  Lane l takes chunks l + 64 (u + 4 p) of the tile; each chunk's V
+// terms are summed pairwise, then added to accumulator u (one per chunk
+// slot, across the P passes); the 4 accumulators fold pairwise, then across
+// the wave.  Every float sum on the way has depth <= 19.
+template <int TMPL, typename T, int V>
 __device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long k, int lane) {
-  constexpr long long TT = 64LL * V * U;
+  constexpr int U = 4;
   constexpr bool NY = TMPL == 1 || TMPL == 4, NW = TMPL == 7;
   const T* X = (const T*)J.x;
   const T* Y = (const T*)J.y;
   const T* W = (const T*)J.w;
+  const hipmr_geom g = hipmr_job_geom(J);
   const long long n = J.n;
-  const bool vec_ok = J.head >= 0;
-  const long long ab = vec_ok ? (J.head < n ? J.head : n) : 0;
-  const long long ts = k == 0 ? 0 : ab + k * TT;
-  const long long te = ab + (k + 1) * TT < n ? ab + (k + 1) * TT : n;
+  const long long ts = k == 0 ? 0 : g.ab + k * g.tt;
+  const long long te = g.ab + (k + 1) * g.tt < n ? g.ab + (k + 1) * g.tt : n;
   const float neutral = TMPL == 3 ? -__builtin_huge_valf() : 0.0f;
-  float s0[U], s1[U];
+  float2 acc[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) { s0[u] = neutral; s1[u] = 0.0f; }
-  if (!vec_ok) {                         // arrays without a common alignment
-    for (long long e = ts + lane; e < te; e += 64)
-      hipmr_job_elem<TMPL>(s0[0], s1[0], (float)X[e], NY ? (float)Y[e] : 0.0f,
-                           NW ? (float)W[e] : 0.0f, J.a, J.b);
+  for (int u = 0; u < U; ++u) acc[u] = make_float2(neutral, 0.0f);
+  auto elem = [&](long long e) {
+    return hipmr_job_term<TMPL>((float)X[e], NY ? (float)Y[e] : 0.0f, NW ? (float)W[e] : 0.0f, J.a, J.b);
+  };
+  if (J.head < 0) {                      // arrays without a common alignment: single elements
+    int u = 0;
+    for (long long e = ts + lane; e < te; e += 64, u = (u + 1) & (U - 1))
+      acc[u] = hipmr_job_comb2<TMPL>(acc[u], elem(e));
   } else {
-    const long long hend = k == 0 ? ab : ts;
+    const long long hend = k == 0 ? g.ab : ts;
     const long long nch = te > hend ? (te - hend) / V : 0;
     const long long tail = hend + nch * V;
-    if (lane < hend - ts) {
-      const long long e = ts + lane;
-      hipmr_job_elem<TMPL>(s0[0], s1[0], (float)X[e], NY ? (float)Y[e] : 0.0f,
-                           NW ? (float)W[e] : 0.0f, J.a, J.b);
-    }
-    hipmr_pack<T, V> px[U], py[U], pw[U];
+    if (lane < hend - ts) acc[0] = hipmr_job_comb2<TMPL>(acc[0], elem(ts + lane));
+    for (int p = 0; p < g.passes; ++p) {
+      hipmr_pack<T, V> px[U], py[U], pw[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long long c = lane + 64 * u;
-      if (c < nch) {
-        const long long off = hend + c * V;
-        hipmr_load<true>(px[u], X + off);
-        if constexpr (NY) hipmr_load<true>(py[u], Y + off);
-        if constexpr (NW) hipmr_load<true>(pw[u], W + off);
+      for (int u = 0; u < U; ++u) {
+        const long long c = lane + 64 * (u + U * p);
+        if (c < nch) {
+          const long long off = hend + c * V;
+          hipmr_load<true>(px[u], X + off);
+          if constexpr (NY) hipmr_load<true>(py[u], Y + off);
+          if constexpr (NW) hipmr_load<true>(pw[u], W + off);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long c = lane + 64 * (u + U * p);
+        if (c < nch) {
+          float2 t[V];
+#pragma unroll
+          for (int j = 0; j < V; ++j)
+            t[j] = hipmr_job_term<TMPL>((float)px[u].v[j], NY ? (float)py[u].v[j] : 0.0f,
+                                        NW ? (float)pw[u].v[j] : 0.0f, J.a, J.b);
+#pragma unroll
+          for (int w = 1; w < V; w *= 2) {
+#pragma unroll
+            for (int j = 0; j + w < V; j += 2 * w) t[j] = hipmr_job_comb2<TMPL>(t[j], t[j + w]);
+          }
+          acc[u] = hipmr_job_comb2<TMPL>(acc[u], t[0]);
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long long c = lane + 64 * u;
-      if (c < nch) {
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-          hipmr_job_elem<TMPL>(s0[u], s1[u], (float)px[u].v[j], NY ? (float)py[u].v[j] : 0.0f,
-                               NW ? (float)pw[u].v[j] : 0.0f, J.a, J.b);
-      }
-    }
-    if (lane < te - tail) {
-      const long long e = tail + lane;
-      hipmr_job_elem<TMPL>(s0[U - 1], s1[U - 1], (float)X[e], NY ? (float)Y[e] : 0.0f,
-                           NW ? (float)W[e] : 0.0f, J.a, J.b);
-    }
+    if (lane < te - tail) acc[U - 1] = hipmr_job_comb2<TMPL>(acc[U - 1], elem(tail + lane));
   }
+  acc[0] = hipmr_job_comb2<TMPL>(acc[0], acc[1]);
+  acc[2] = hipmr_job_comb2<TMPL>(acc[2], acc[3]);
+  float2 r = hipmr_job_comb2<TMPL>(acc[0], acc[2]);
 #pragma unroll
-  for (int s = 1; s < U; s *= 2) {
-#pragma unroll
-    for (int u = 0; u + s < U; u += 2 * s) {
-      s0[u] = hipmr_job_comb<TMPL>(s0[u], s0[u + s]);
-      s1[u] += s1[u + s];
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    s0[0] = hipmr_job_comb<TMPL>(s0[0], __shfl_xor(s0[0], m, 64));
-    s1[0] += __shfl_xor(s1[0], m, 64);
-  }
-  return make_float2(s0[0], s1[0]);
+  for (int m = 32; m >= 1; m >>= 1)
+    r = hipmr_job_comb2<TMPL>(r, make_float2(__shfl_xor(r.x, m, 64), __shfl_xor(r.y, m, 64)));
+  return r;
 }
-
-constexpr int HIPMR_TILE_F32 = 64 * 4 * 4, HIPMR_TILE_BF16 = 64 * 8 * 4;
 
 __device__ __forceinline__ float2 hipmr_job_dispatch(const hipmr_sjob& J, long long k, int lane) {
   const bool bf = J.dtype == @@BF16CODE@@;
   switch (J.tmpl * 2 + (bf ? 1 : 0)) {
-    case 0: return hipmr_job_tile<0, float, 4, 4>(J, k, lane);
-    case 1: return hipmr_job_tile<0, hipmr_bf16, 8, 4>(J, k, lane);
-    case 2: return hipmr_job_tile<1, float, 4, 4>(J, k, lane);
-    case 3: return hipmr_job_tile<1, hipmr_bf16, 8, 4>(J, k, lane);
-    case 4: return hipmr_job_tile<2, float, 4, 4>(J, k, lane);
-    case 5: return hipmr_job_tile<2, hipmr_bf16, 8, 4>(J, k, lane);
-    case 6: return hipmr_job_tile<3, float, 4, 4>(J, k, lane);
-    case 7: return hipmr_job_tile<3, hipmr_bf16, 8, 4>(J, k, lane);
-    case 8: return hipmr_job_tile<4, float, 4, 4>(J, k, lane);
-    case 9: return hipmr_job_tile<4, hipmr_bf16, 8, 4>(J, k, lane);
-    case 10: return hipmr_job_tile<5, float, 4, 4>(J, k, lane);
-    case 11: return hipmr_job_tile<5, hipmr_bf16, 8, 4>(J, k, lane);
-    case 12: return hipmr_job_tile<6, float, 4, 4>(J, k, lane);
-    case 13: return hipmr_job_tile<6, hipmr_bf16, 8, 4>(J, k, lane);
-    case 14: return hipmr_job_tile<7, float, 4, 4>(J, k, lane);
-    default: return hipmr_job_tile<7, hipmr_bf16, 8, 4>(J, k, lane);
+    case 0: return hipmr_job_tile<0, float, 4>(J, k, lane);
+    case 1: return hipmr_job_tile<0, hipmr_bf16, 8>(J, k, lane);
+    case 2: return hipmr_job_tile<1, float, 4>(J, k, lane);
+    case 3: return hipmr_job_tile<1, hipmr_bf16, 8>(J, k, lane);
+    case 4: return hipmr_job_tile<2, float, 4>(J, k, lane);
+    case 5: return hipmr_job_tile<2, hipmr_bf16, 8>(J, k, lane);
+    case 6: return hipmr_job_tile<3, float, 4>(J, k, lane);
+    case 7: return hipmr_job_tile<3, hipmr_bf16, 8>(J, k, lane);
+    case 8: return hipmr_job_tile<4, float, 4>(J, k, lane);
+    case 9: return hipmr_job_tile<4, hipmr_bf16, 8>(J, k, lane);
+    case 10: return hipmr_job_tile<5, float, 4>(J, k, lane);
+    case 11: return hipmr_job_tile<5, hipmr_bf16, 8>(J, k, lane);
+    case 12: return hipmr_job_tile<6, float, 4>(J, k, lane);
+    case 13: return hipmr_job_tile<6, hipmr_bf16, 8>(J, k, lane);
+    case 14: return hipmr_job_tile<7, float, 4>(J, k, lane);
+    default: return hipmr_job_tile<7, hipmr_bf16, 8>(J, k, lane);
   }
 }
 
-// Final fold of one job's tile partials (in tile order, FP64) and its finish.
+// Final fold of one job's tile partials [t0, t1) by one block of 256 threads
+// (FP64): thread k folds tiles t0 + k, t0 + k + 256, ... in order (eight
+// loads in flight), then the wave butterfly, then the four waves in order;
+// thread 0 finishes the job (sqrt, ratio).
 __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, int t1,
-                                                 const float2* __restrict__ tpart, int lane) {
+                                                 const float2* __restrict__ tpart,
+                                                 unsigned long long* flag, unsigned long long seq) {
+  __shared__ double hipmr_fin[2][4];
   const bool mx = J.tmpl == 3;
   double a0 = mx ? -__builtin_huge_val() : 0.0, a1 = 0.0;
-  for (int t = t0 + lane; t < t1; t += 64) {
-    const float2 p = tpart[t];
-    a0 = mx ? __builtin_elementwise_maximum(a0, (double)p.x) : a0 + (double)p.x;
-    a1 += (double)p.y;
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += 256 * 8) {
+    float2 p[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (t + 256 * k < t1) p[k] = tpart[t + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (t + 256 * k < t1) {
+        a0 = mx ? __builtin_elementwise_maximum(a0, (double)p[k].x) : a0 + (double)p[k].x;
+        a1 += (double)p[k].y;
+      }
+    }
   }
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
@@ -206,20 +244,26 @@ __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, in
     a0 = mx ? __builtin_elementwise_maximum(a0, o0) : a0 + o0;
     a1 += o1;
   }
-  if (lane == 0) {
-    double r = a0;
-    if (J.tmpl == 2) r = sqrt(a0);
-    else if (J.tmpl == 7) r = a0 / a1;
-    *J.out = r;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    hipmr_fin[0][w] = a0;
+    hipmr_fin[1][w] = a1;
   }
-}
-
-__device__ __forceinline__ int hipmr_job_tiles(const hipmr_sjob& J) {
-  if (J.n <= 0) return 0;
-  const long long tt = J.dtype == @@BF16CODE@@ ? HIPMR_TILE_BF16 : HIPMR_TILE_F32;
-  const long long ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
-  const long long t = (J.n - ab + tt - 1) / tt;
-  return t < 1 ? 1 : (int)t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = hipmr_fin[0][0], q = hipmr_fin[1][0];
+    for (int k = 1; k < 4; ++k) {
+      r = mx ? __builtin_elementwise_maximum(r, hipmr_fin[0][k]) : r + hipmr_fin[0][k];
+      q += hipmr_fin[1][k];
+    }
+    if (J.tmpl == 2) r = sqrt(r);
+    else if (J.tmpl == 7) r = r / q;
+    *J.out = r;
+    // the result is visible system-wide before the job's completion flag (in
+    // host memory) changes
+    __threadfence_system();
+    *(volatile unsigned long long*)flag = seq;
+  }
 }
 
 // Batched stage 1: persistent waves over the batch's tiles.
@@ -251,13 +295,12 @@ extern "C" __global__ void __launch_bounds__(256)
 // Batched stage 2: one wave per job.
 extern "C" __global__ void __launch_bounds__(256)
 @@PREFIX@@_s2(const hipmr_sjob* __restrict__ jobs, int njobs, int total_tiles,
-              const float2* __restrict__ tpart)
+              const float2* __restrict__ tpart, unsigned long long* flags, unsigned long long seq)
 {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= njobs) return;
+  const int j = blockIdx.x;                     // one block per job (grid = njobs)
   const hipmr_sjob J = jobs[j];
   const int t1 = j + 1 < njobs ? jobs[j + 1].tile0 : total_tiles;
-  hipmr_job_finish(J, J.tile0, t1, tpart, threadIdx.x & 63);
+  hipmr_job_finish(J, J.tile0, t1, tpart, flags + j, seq);
 }
 
 // Small batches: the descriptors travel by value in the kernel arguments
@@ -282,13 +325,13 @@ extern "C" __global__ void __launch_bounds__(256)
 }
 
 extern "C" __global__ void __launch_bounds__(256)
-@@PREFIX@@_i2(const hipmr_jobs_inline B, const float2* __restrict__ tpart)
+@@PREFIX@@_i2(const hipmr_jobs_inline B, const float2* __restrict__ tpart,
+              unsigned long long* flags, unsigned long long seq)
 {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= B.njobs) return;
+  const int j = blockIdx.x;                     // one block per job (grid = njobs)
   const hipmr_sjob J = B.jobs[j];
   const int t1 = j + 1 < B.njobs ? B.jobs[j + 1].tile0 : B.total_tiles;
-  hipmr_job_finish(J, J.tile0, t1, tpart, threadIdx.x & 63);
+  hipmr_job_finish(J, J.tile0, t1, tpart, flags + j, seq);
 }
 
 // One job, descriptor by value: the one-launch-pair-per-job path.
@@ -296,17 +339,18 @@ extern "C" __global__ void __launch_bounds__(256)
 @@PREFIX@@_one1(hipmr_sjob J, float2* __restrict__ tpart)
 {
   const int lane = threadIdx.x & 63;
-  const int tiles = hipmr_job_tiles(J);
+  const int tiles = hipmr_job_geom(J).tiles;
   for (int t = blockIdx.x * 4 + (threadIdx.x >> 6); t < tiles; t += gridDim.x * 4) {
     const float2 r = hipmr_job_dispatch(J, t, lane);
     if (lane == 0) tpart[t] = r;
   }
 }
 
-extern "C" __global__ void __launch_bounds__(64)
-@@PREFIX@@_one2(hipmr_sjob J, const float2* __restrict__ tpart)
+extern "C" __global__ void __launch_bounds__(256)
+@@PREFIX@@_one2(hipmr_sjob J, const float2* __restrict__ tpart, unsigned long long* flags,
+                unsigned long long seq)
 {
-  hipmr_job_finish(J, 0, hipmr_job_tiles(J), tpart, threadIdx.x & 63);
+  hipmr_job_finish(J, 0, hipmr_job_geom(J).tiles, tpart, flags, seq);
 }
 )HIP";
 
@@ -337,11 +381,15 @@ int job_head(const hipmr_sjob& j) {
     return -1;
 }
 
+// Tiles of a job; the same geometry as hipmr_job_geom in the kernels.
 int job_tiles(const hipmr_sjob& j, int head) {
     if (j.n <= 0) return 0;
-    const long long tt = tile_elems(j.dtype);
+    const long long tt0 = tile_elems(j.dtype);
     const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
-    const long long t = (j.n - ab + tt - 1) / tt;
+    const long long body = j.n - ab;
+    long long p = 1;
+    while (head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 2048) p *= 2;
+    const long long t = (body + tt0 * p - 1) / (tt0 * p);
     return (int)std::max<long long>(t, 1);
 }
 
@@ -365,6 +413,7 @@ hipmr_server_config resolved(const hipmr_server_config* in) {
     if (c.max_batch_jobs == 0) c.max_batch_jobs = 1024;
     if (c.max_batch_tiles == 0) c.max_batch_tiles = 1 << 18;
     if (c.blocks_per_cu == 0) c.blocks_per_cu = 8;
+    if (c.max_batch_bytes == 0) c.max_batch_bytes = 16ull << 20;
     return c;
 }
 
@@ -413,6 +462,9 @@ struct hipmr_server {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
         DevJob* host_desc = nullptr;    // pinned host memory
+        uint64_t* flags = nullptr;      // per-job completion flags (host memory, mapped)
+        uint64_t* dev_flags = nullptr;  // the same memory, as the device sees it
+        uint64_t seq = 0;               // the current batch's flag value
         DevJob* dev_desc = nullptr;     // in the caller's workspace
         void* tpart = nullptr;          // in the caller's workspace
         std::vector<Pending> jobs;
@@ -462,7 +514,8 @@ struct hipmr_server {
 
     hipmr_status launch_batch(Slot& s) {
         const int nj = (int)s.jobs.size();
-        if (cfg.max_batch_jobs == 1) {
+        ++s.seq;
+        if (nj == 1) {              // one job: its descriptor by value
             const Pending& p = s.jobs[0];
             DevJob d{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
                      p.job.out, p.job.a, p.job.b};
@@ -470,8 +523,8 @@ struct hipmr_server {
             void* a1[2] = {&d, &s.tpart};
             hipError_t e = hipModuleLaunchKernel(f_one1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
             if (e == hipSuccess) {
-                void* a2[2] = {&d, &s.tpart};
-                e = hipModuleLaunchKernel(f_one2, 1, 1, 1, 64, 1, 1, 0, s.stream, a2, nullptr);
+                void* a2[4] = {&d, &s.tpart, &s.dev_flags, &s.seq};
+                e = hipModuleLaunchKernel(f_one2, 1, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
             }
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         } else if (nj <= kInlineJobs) {
@@ -488,9 +541,9 @@ struct hipmr_server {
             int grid = std::max(1, std::min(cfg.blocks_per_cu * cus, (tile0 + 3) / 4));
             void* a1[2] = {&b, &s.tpart};
             hipError_t e = hipModuleLaunchKernel(f_i1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
-            void* a2[2] = {&b, &s.tpart};
+            void* a2[4] = {&b, &s.tpart, &s.dev_flags, &s.seq};
             if (e == hipSuccess)
-                e = hipModuleLaunchKernel(f_i2, (nj + 3) / 4, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+                e = hipModuleLaunchKernel(f_i2, nj, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         } else {
             int tile0 = 0;
@@ -507,9 +560,9 @@ struct hipmr_server {
             void* a1[4] = {&s.dev_desc, (void*)&nj, &total, &s.tpart};
             if (e == hipSuccess)
                 e = hipModuleLaunchKernel(f_s1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
-            void* a2[4] = {&s.dev_desc, (void*)&nj, &total, &s.tpart};
+            void* a2[6] = {&s.dev_desc, (void*)&nj, &total, &s.tpart, &s.dev_flags, &s.seq};
             if (e == hipSuccess)
-                e = hipModuleLaunchKernel(f_s2, (nj + 3) / 4, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+                e = hipModuleLaunchKernel(f_s2, nj, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         }
         hipError_t e = hipEventRecord(s.done, s.stream);
@@ -543,10 +596,22 @@ struct hipmr_server {
         // completions
         for (Slot& s : slots) {
             if (!s.busy) continue;
-            hipError_t q = hipEventQuery(s.done);
-            if (q == hipErrorNotReady) continue;
+            // every job's flag carries this batch's sequence number once its
+            // result is written; the event is only a watchdog for errors
+            bool all = true;
+            for (size_t k = 0; k < s.jobs.size() && all; ++k)
+                all = *(volatile uint64_t*)&s.flags[k] == s.seq;
+            int32_t st = HIPMR_OK;
+            if (!all) {
+                if (now_ns() - s.launch_ns < kWatchdogNs) continue;
+                hipError_t q = hipEventQuery(s.done);
+                if (q == hipErrorNotReady) continue;
+                all = true;
+                for (size_t k = 0; k < s.jobs.size() && all; ++k)
+                    all = *(volatile uint64_t*)&s.flags[k] == s.seq;
+                if (q != hipSuccess || !all) st = HIPMR_E_HIP;
+            }
             const int64_t done = now_ns();
-            const int32_t st = q == hipSuccess ? HIPMR_OK : HIPMR_E_HIP;
             for (const Pending& p : s.jobs) {
                 admitted -= p.bytes;
                 complete(p, st, (int32_t)s.jobs.size(), s.launch_ns, done);
@@ -559,12 +624,16 @@ struct hipmr_server {
         for (Slot& s : slots) {
             if (s.busy || waiting.empty()) continue;
             int tiles = 0;
+            uint64_t bytes = 0;
             while (!waiting.empty() && (int)s.jobs.size() < cfg.max_batch_jobs) {
                 const Pending& p = waiting.front();
                 if (admitted + p.bytes > cfg.hbm_budget_bytes) break;
-                if (!s.jobs.empty() && tiles + p.tiles > cfg.max_batch_tiles) break;
+                if (!s.jobs.empty() &&
+                    (tiles + p.tiles > cfg.max_batch_tiles || bytes + p.bytes > cfg.max_batch_bytes))
+                    break;
                 admitted += p.bytes;
                 tiles += p.tiles;
+                bytes += p.bytes;
                 s.jobs.push_back(p);
                 waiting.pop_front();
             }
@@ -682,8 +751,12 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc((void**)&sl.host_desc, (size_t)c.max_batch_jobs * sizeof(DevJob),
-                          hipHostMallocDefault) != hipSuccess)
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&sl.flags, (size_t)c.max_batch_jobs * sizeof(uint64_t),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&sl.dev_flags, sl.flags, 0) != hipSuccess)
             return fail(HIPMR_E_HIP, "creating the serving streams, events or pinned buffers failed");
+        std::memset(sl.flags, 0, (size_t)c.max_batch_jobs * sizeof(uint64_t));
         sl.dev_desc = (DevJob*)(base + (size_t)k * slot_bytes(c));
         sl.tpart = base + (size_t)k * slot_bytes(c) + align256((size_t)c.max_batch_jobs * sizeof(DevJob));
     }
@@ -805,6 +878,7 @@ void hipmr_server_destroy(hipmr_server_t s) {
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.host_desc) (void)hipHostFree(sl.host_desc);
+        if (sl.flags) (void)hipHostFree(sl.flags);
     }
     if (s->module) (void)hipModuleUnload(s->module);
     delete s;

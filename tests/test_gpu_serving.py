@@ -89,9 +89,11 @@ def oracle_check(k, got, sched, pool):
 
 @pytest.fixture(scope="module")
 def mix(dev, pool):
-    sched = workloads.serving_schedule(10000, 0.05, pool_n=POOL_N, log2_max=20)
+    # 100k jobs/s on two streams: arrivals outpace single-job service, so jobs
+    # that arrive while others run are packed into the next free slot
+    sched = workloads.serving_schedule(100000, 0.005, pool_n=POOL_N, log2_max=20)
     out = torch.full((len(sched["n"]),), float("nan"), dtype=torch.float64, device=dev)
-    server = hm.Server(nstreams=4, max_batch_jobs=1024)
+    server = hm.Server(nstreams=2, max_batch_jobs=1024)
     done = server.run_schedule(make_jobs(server, sched, pool, out))
     torch.cuda.synchronize()
     server.close()
