@@ -331,8 +331,8 @@ typedef struct hipmr_server_config {
     int32_t nstreams;            /* batches in flight, one stream each (1..16); 0: 4                */
     int32_t max_batch_jobs;      /* jobs per batch (1..4096; 1 = one launch pair per job); 0: 1024  */
     int32_t max_batch_tiles;     /* tiles per batch (a tile is 1024 float32 / 2048 bfloat16
-                                    elements, 2-8 times that in jobs of over 2^21 / 2^22
-                                    elements, so that no job has more than 2048); 0: 2^18         */
+                                    elements, 2-8 times that in jobs of over 2^23 / 2^24
+                                    elements, so that no job has more than 8192); 0: 2^18         */
     int32_t blocks_per_cu;       /* persistent grid of the tile kernel; 0: 8                        */
     uint64_t max_batch_bytes;    /* input bytes per batch of two or more jobs (a larger job runs
                                     alone), so small jobs do not wait on large ones; 0: 16 MiB     */
@@ -363,8 +363,8 @@ size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
  * one block per job folding its tiles in a fixed order.  A job's tiles depend
  * only on the job, so its result is bitwise the same alone or in any mix.
  * Completion is observed through per-job flags in mapped host memory that the
- * folding block writes after the result (one event per batch is a watchdog
- * for errors).  Inputs stay resident: jobs name device arrays.  The server
+ * folding block writes after the result (a stream query is the watchdog for
+ * errors).  Inputs stay resident: jobs name device arrays.  The server
  * allocates pinned host memory for descriptors and flags (not device memory).
  * Errors: E_INVALID (config), E_WORKSPACE, E_COMPILE, E_HIP. */
 hipmr_status hipmr_server_create(const hipmr_server_config *cfg, void *workspace,

@@ -812,21 +812,33 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   };
   const int hipmr_total_tiles = hipmr_ts(hipmr_nseg);
   const int hipmr_nwaves = gridDim.x * (HIPMR_B / 64);
-  for (int hipmr_t = blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6); hipmr_t < hipmr_total_tiles; hipmr_t += hipmr_nwaves) {
-    // segment of the tile: the last s with tile_start[s] <= tile (64-way ballot search)
+  // segment of a tile: the last s with tile_start[s] <= tile (64-way ballot search)
+  auto hipmr_find = [&](int hipmr_tile) -> int {
     int hipmr_lo = 0, hipmr_hi = hipmr_nseg - 1;
     while (hipmr_lo < hipmr_hi) {
       const int hipmr_step = (hipmr_hi - hipmr_lo + 64) / 64;
       const int hipmr_cand = hipmr_lo + hipmr_lane * hipmr_step;
-      const bool hipmr_pred = hipmr_cand <= hipmr_hi && hipmr_ts(hipmr_cand) <= hipmr_t;
+      const bool hipmr_pred = hipmr_cand <= hipmr_hi && hipmr_ts(hipmr_cand) <= hipmr_tile;
       const unsigned long long hipmr_m = __ballot(hipmr_pred);
       const int hipmr_k = 63 - __builtin_clzll(hipmr_m);
       hipmr_lo = hipmr_lo + hipmr_k * hipmr_step;
       hipmr_hi = hipmr_lo + hipmr_step - 1 < hipmr_hi ? hipmr_lo + hipmr_step - 1 : hipmr_hi;
     }
-    const int hipmr_s = hipmr_lo;
+    return hipmr_lo;
+  };
+  int hipmr_t = blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6);
+  // the segment and raw bounds of the wave's next tile are fetched while the
+  // current tile's loads are in flight
+  int hipmr_s = 0;
+  long long hipmr_oa = 0, hipmr_ob = 0;
+  if (hipmr_t < hipmr_total_tiles) {
+    hipmr_s = hipmr_find(hipmr_t);
+    hipmr_oa = hipmr_offsets[hipmr_s];
+    hipmr_ob = hipmr_offsets[hipmr_s + 1];
+  }
+  for (; hipmr_t < hipmr_total_tiles; hipmr_t += hipmr_nwaves) {
     long long hipmr_sa, hipmr_sb, hipmr_sab;
-    hipmr_seg_bounds(hipmr_offsets, hipmr_s, hipmr_total, hipmr_head, HIPMR_V, hipmr_sa, hipmr_sb, hipmr_sab);
+    hipmr_seg_clamp(hipmr_oa, hipmr_ob, hipmr_total, hipmr_head, HIPMR_V, hipmr_sa, hipmr_sb, hipmr_sab);
     const long long hipmr_k = hipmr_t - hipmr_ts(hipmr_s);
     const long long hipmr_tstart = hipmr_k == 0 ? hipmr_sa : hipmr_sab + hipmr_k * HIPMR_T;
     const long long hipmr_hend = hipmr_k == 0 ? hipmr_sab : hipmr_tstart;
@@ -848,6 +860,12 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
         const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
         @@LOADS@@
       }
+    }
+    const int hipmr_tn = hipmr_t + hipmr_nwaves;
+    if (hipmr_tn < hipmr_total_tiles) {
+      hipmr_s = hipmr_find(hipmr_tn);
+      hipmr_oa = hipmr_offsets[hipmr_s];
+      hipmr_ob = hipmr_offsets[hipmr_s + 1];
     }
 #pragma unroll
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {

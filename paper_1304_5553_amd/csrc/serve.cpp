@@ -17,10 +17,10 @@
 //       2. one block per job folding that job's tile partials in a fixed
 //          order and finishing the job (sqrt, ratio);
 //   - completion is observed through per-job flags in mapped host memory,
-//     written by the finishing block after the result (an event per batch
+//     written by the finishing block after the result (querying the stream
 //     serves as a watchdog for errors).
 // A job's tiles depend only on the job (its length, dtype and alignment; big
-// jobs get longer tiles so that none has more than 2048), so its result is
+// jobs get longer tiles so that none has more than 8192), so its result is
 // bitwise the same alone or in any mix.  A batch of one job passes its
 // descriptor by value; with max_batch_jobs = 1 every job runs that way, one
 // launch pair per job: the baseline.
@@ -41,10 +41,11 @@ using namespace hipmr;
 
 namespace {
 
-constexpr int kServeBlock = 256;
+constexpr int kServeBlock = 256;          // tile kernels: 4 waves, one tile per wave at a time
+constexpr int kFinBlock = 1024;           // final fold: one block per job
 constexpr int kMaxBatchJobs = 4096;      // LDS table of job tile offsets
 constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
-constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, ask the event
+constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
 // hipmr_sjob struct in the kernels below).
@@ -103,7 +104,7 @@ __device__ __forceinline__ float2 hipmr_job_comb2(float2 a, float2 b) {
 // elements (all arrays 16-byte aligned after them; 0 when they share no
 // alignment), then tiles of `tt` elements = P passes of 64 lanes x 4 chunks x
 // V elements.  P (1, 2, 4 or 8) is the smallest that keeps the job at or
-// under 2048 tiles; arrays without a common alignment use P = 1.
+// under 8192 tiles; arrays without a common alignment use P = 1.
 struct hipmr_geom { long long ab, tt; int passes, tiles; };
 
 __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
@@ -112,7 +113,7 @@ __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
   g.ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
   const long long body = J.n - g.ab;
   int p = 1;
-  while (J.head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 2048) p *= 2;
+  while (J.head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
   g.passes = p;
   g.tt = tt0 * p;
   const long long t = (body + g.tt - 1) / g.tt;
@@ -215,24 +216,28 @@ __device__ __forceinline__ float2 hipmr_job_dispatch(const hipmr_sjob& J, long l
   }
 }
 
-// Final fold of one job's tile partials [t0, t1) by one block of 256 threads
-// (FP64): thread k folds tiles t0 + k, t0 + k + 256, ... in order (eight
-// loads in flight), then the wave butterfly, then the four waves in order;
-// thread 0 finishes the job (sqrt, ratio).
+// Final fold of one job's tile partials [t0, t1) by one block of 1024
+// threads (FP64): thread k folds tiles t0 + k, t0 + k + 1024, ... in order
+// (eight loads in flight, so one round covers 8192 tiles), then the wave
+// butterfly, then the 16 waves in order; thread 0 finishes the job (sqrt,
+// ratio).
+constexpr int HIPMR_FIN_BLOCK = 1024;
+
 __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, int t1,
                                                  const float2* __restrict__ tpart,
                                                  unsigned long long* flag, unsigned long long seq) {
-  __shared__ double hipmr_fin[2][4];
+  constexpr int NW = HIPMR_FIN_BLOCK / 64;
+  __shared__ double hipmr_fin[2][NW];
   const bool mx = J.tmpl == 3;
   double a0 = mx ? -__builtin_huge_val() : 0.0, a1 = 0.0;
-  for (int t = t0 + (int)threadIdx.x; t < t1; t += 256 * 8) {
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += HIPMR_FIN_BLOCK * 8) {
     float2 p[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (t + 256 * k < t1) p[k] = tpart[t + 256 * k];
+      if (t + HIPMR_FIN_BLOCK * k < t1) p[k] = tpart[t + HIPMR_FIN_BLOCK * k];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if (t + 256 * k < t1) {
+      if (t + HIPMR_FIN_BLOCK * k < t1) {
         a0 = mx ? __builtin_elementwise_maximum(a0, (double)p[k].x) : a0 + (double)p[k].x;
         a1 += (double)p[k].y;
       }
@@ -252,7 +257,7 @@ __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, in
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = hipmr_fin[0][0], q = hipmr_fin[1][0];
-    for (int k = 1; k < 4; ++k) {
+    for (int k = 1; k < NW; ++k) {
       r = mx ? __builtin_elementwise_maximum(r, hipmr_fin[0][k]) : r + hipmr_fin[0][k];
       q += hipmr_fin[1][k];
     }
@@ -293,7 +298,7 @@ extern "C" __global__ void __launch_bounds__(256)
 }
 
 // Batched stage 2: one wave per job.
-extern "C" __global__ void __launch_bounds__(256)
+extern "C" __global__ void __launch_bounds__(1024)
 @@PREFIX@@_s2(const hipmr_sjob* __restrict__ jobs, int njobs, int total_tiles,
               const float2* __restrict__ tpart, unsigned long long* flags, unsigned long long seq)
 {
@@ -324,7 +329,7 @@ extern "C" __global__ void __launch_bounds__(256)
   }
 }
 
-extern "C" __global__ void __launch_bounds__(256)
+extern "C" __global__ void __launch_bounds__(1024)
 @@PREFIX@@_i2(const hipmr_jobs_inline B, const float2* __restrict__ tpart,
               unsigned long long* flags, unsigned long long seq)
 {
@@ -346,7 +351,7 @@ extern "C" __global__ void __launch_bounds__(256)
   }
 }
 
-extern "C" __global__ void __launch_bounds__(256)
+extern "C" __global__ void __launch_bounds__(1024)
 @@PREFIX@@_one2(hipmr_sjob J, const float2* __restrict__ tpart, unsigned long long* flags,
                 unsigned long long seq)
 {
@@ -388,7 +393,7 @@ int job_tiles(const hipmr_sjob& j, int head) {
     const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
     const long long body = j.n - ab;
     long long p = 1;
-    while (head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 2048) p *= 2;
+    while (head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
     const long long t = (body + tt0 * p - 1) / (tt0 * p);
     return (int)std::max<long long>(t, 1);
 }
@@ -460,7 +465,6 @@ struct hipmr_server {
     };
     struct Slot {
         hipStream_t stream = nullptr;
-        hipEvent_t done = nullptr;
         DevJob* host_desc = nullptr;    // pinned host memory
         uint64_t* flags = nullptr;      // per-job completion flags (host memory, mapped)
         uint64_t* dev_flags = nullptr;  // the same memory, as the device sees it
@@ -524,7 +528,7 @@ struct hipmr_server {
             hipError_t e = hipModuleLaunchKernel(f_one1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
             if (e == hipSuccess) {
                 void* a2[4] = {&d, &s.tpart, &s.dev_flags, &s.seq};
-                e = hipModuleLaunchKernel(f_one2, 1, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+                e = hipModuleLaunchKernel(f_one2, 1, 1, 1, kFinBlock, 1, 1, 0, s.stream, a2, nullptr);
             }
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         } else if (nj <= kInlineJobs) {
@@ -543,7 +547,7 @@ struct hipmr_server {
             hipError_t e = hipModuleLaunchKernel(f_i1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
             void* a2[4] = {&b, &s.tpart, &s.dev_flags, &s.seq};
             if (e == hipSuccess)
-                e = hipModuleLaunchKernel(f_i2, nj, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+                e = hipModuleLaunchKernel(f_i2, nj, 1, 1, kFinBlock, 1, 1, 0, s.stream, a2, nullptr);
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         } else {
             int tile0 = 0;
@@ -562,11 +566,9 @@ struct hipmr_server {
                 e = hipModuleLaunchKernel(f_s1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
             void* a2[6] = {&s.dev_desc, (void*)&nj, &total, &s.tpart, &s.dev_flags, &s.seq};
             if (e == hipSuccess)
-                e = hipModuleLaunchKernel(f_s2, nj, 1, 1, kServeBlock, 1, 1, 0, s.stream, a2, nullptr);
+                e = hipModuleLaunchKernel(f_s2, nj, 1, 1, kFinBlock, 1, 1, 0, s.stream, a2, nullptr);
             if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
         }
-        hipError_t e = hipEventRecord(s.done, s.stream);
-        if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipEventRecord: ") + hipGetErrorString(e));
         s.launch_ns = now_ns();
         s.busy = true;
         return HIPMR_OK;
@@ -597,14 +599,15 @@ struct hipmr_server {
         for (Slot& s : slots) {
             if (!s.busy) continue;
             // every job's flag carries this batch's sequence number once its
-            // result is written; the event is only a watchdog for errors
+            // result is written; the stream is queried only as a watchdog for
+            // errors
             bool all = true;
             for (size_t k = 0; k < s.jobs.size() && all; ++k)
                 all = *(volatile uint64_t*)&s.flags[k] == s.seq;
             int32_t st = HIPMR_OK;
             if (!all) {
                 if (now_ns() - s.launch_ns < kWatchdogNs) continue;
-                hipError_t q = hipEventQuery(s.done);
+                hipError_t q = hipStreamQuery(s.stream);
                 if (q == hipErrorNotReady) continue;
                 all = true;
                 for (size_t k = 0; k < s.jobs.size() && all; ++k)
@@ -749,13 +752,12 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
         auto& sl = s->slots[k];
         // default-priority, non-blocking streams
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc((void**)&sl.host_desc, (size_t)c.max_batch_jobs * sizeof(DevJob),
                           hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&sl.flags, (size_t)c.max_batch_jobs * sizeof(uint64_t),
                           hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
             hipHostGetDevicePointer((void**)&sl.dev_flags, sl.flags, 0) != hipSuccess)
-            return fail(HIPMR_E_HIP, "creating the serving streams, events or pinned buffers failed");
+            return fail(HIPMR_E_HIP, "creating the serving streams or pinned buffers failed");
         std::memset(sl.flags, 0, (size_t)c.max_batch_jobs * sizeof(uint64_t));
         sl.dev_desc = (DevJob*)(base + (size_t)k * slot_bytes(c));
         sl.tpart = base + (size_t)k * slot_bytes(c) + align256((size_t)c.max_batch_jobs * sizeof(DevJob));
@@ -875,7 +877,6 @@ void hipmr_server_destroy(hipmr_server_t s) {
     if (s->worker.joinable()) s->worker.join();
     for (auto& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.host_desc) (void)hipHostFree(sl.host_desc);
         if (sl.flags) (void)hipHostFree(sl.flags);
