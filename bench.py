@@ -44,8 +44,8 @@ def parse():
                    help="skip the precision, batching and serving measurements")
     p.add_argument("--extensions", default="precision,batched,served",
                    help="comma list of the extension measurements to run")
-    p.add_argument("--serving-duration", type=float, default=2.0,
-                   help="measured seconds of each serving rate (after 0.5 s of warm-up)")
+    p.add_argument("--serving-duration", type=float, default=5.0,
+                   help="measured seconds of each serving rate (after 1 s of warm-up)")
     p.add_argument("--cpu-sample", type=int, default=1 << 27,
                    help="elements per op for the oracle timing")
     p.add_argument("--ops", default="E1,E2,R1,R2,R3",
@@ -214,19 +214,20 @@ def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
     return res
 
 
-def bench_serving(torch, hm, workloads, dev, duration_s=2.0, warmup_s=0.5):
+def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates=None):
     """Poisson streams at 2k, 10k and 50k jobs/s (8 templates, float32 /
     bfloat16 50/50, n log-uniform over [2^10, 2^24], slices of a resident 2^24
-    pool), replayed open-loop through the continuous-batching loop and
-    through the one-launch-pair-per-job baseline on the same 4 streams;
-    latency = scheduled arrival -> result visible on the host."""
+    pool), plus a 200k jobs/s stress rate beyond them, replayed open-loop
+    through the continuous-batching loop and through the one-launch-pair-per-
+    job baseline on the same 4 streams; latency = scheduled arrival -> the
+    loop sees the job's completion flag (result in device memory)."""
     f32, bf16 = workloads.serving_pool()
     dev_f32 = {k: torch.from_numpy(v).to(dev) for k, v in f32.items()}
     dev_bf16 = {k: torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).to(dev)
                 for k, v in bf16.items()}
     res = {"pool": workloads.N_POOL, "duration_s": duration_s, "warmup_s": warmup_s,
            "budget_bytes": 64 << 30, "nstreams": 4, "rates": {}}
-    for rate in workloads.SERVING_RATES:
+    for rate in rates or (*workloads.SERVING_RATES, 200000):
         sched = workloads.serving_schedule(rate, warmup_s + duration_s)
         m = len(sched["n"])
         es = np.where(sched["bf16"], 2, 4)
@@ -234,6 +235,8 @@ def bench_serving(torch, hm, workloads, dev, duration_s=2.0, warmup_s=0.5):
         job_bytes = sched["n"] * es * arrays
         out = torch.empty(m, dtype=torch.float64, device=dev)
         row = {"jobs": int(m)}
+        if rate not in workloads.SERVING_RATES:
+            row["note"] = "stress rate beyond the configured ones"
         for mode, max_jobs in (("batched", 1024), ("per_job", 1)):
             server = hm.Server(hbm_budget_bytes=64 << 30, nstreams=4, max_batch_jobs=max_jobs)
             jobs = server.jobs(m)

@@ -43,7 +43,7 @@ namespace {
 
 constexpr int kServeBlock = 256;          // tile kernels: 4 waves, one tile per wave at a time
 constexpr int kFinBlock = 1024;           // final fold: one block per job
-constexpr int kMaxBatchJobs = 4096;      // LDS table of job tile offsets
+constexpr int kMaxBatchJobs = 4096;      // jobs per batch (their tile offsets are staged in LDS)
 constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
 
@@ -145,9 +145,11 @@ __device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long 
     return hipmr_job_term<TMPL>((float)X[e], NY ? (float)Y[e] : 0.0f, NW ? (float)W[e] : 0.0f, J.a, J.b);
   };
   if (J.head < 0) {                      // arrays without a common alignment: single elements
-    int u = 0;
-    for (long long e = ts + lane; e < te; e += 64, u = (u + 1) & (U - 1))
-      acc[u] = hipmr_job_comb2<TMPL>(acc[u], elem(e));
+    for (long long e0 = ts + lane; e0 < te; e0 += 64 * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (e0 + 64 * u < te) acc[u] = hipmr_job_comb2<TMPL>(acc[u], elem(e0 + 64 * u));
+    }
   } else {
     const long long hend = k == 0 ? g.ab : ts;
     const long long nch = te > hend ? (te - hend) / V : 0;
@@ -276,7 +278,7 @@ extern "C" __global__ void __launch_bounds__(256)
 @@PREFIX@@_s1(const hipmr_sjob* __restrict__ jobs, int njobs, int total_tiles,
               float2* __restrict__ tpart)
 {
-  __shared__ int hipmr_t0[@@MAXJ@@];
+  extern __shared__ int hipmr_t0[];             // njobs entries (dynamic LDS)
   for (int k = threadIdx.x; k < njobs; k += 256) hipmr_t0[k] = jobs[k].tile0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -437,7 +439,6 @@ std::string serve_source(const std::string& prefix) {
         }
     };
     rep("@@PREFIX@@", prefix);
-    rep("@@MAXJ@@", std::to_string(kMaxBatchJobs));
     rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
     rep("@@NINLINE@@", std::to_string(kInlineJobs));
     return src;
@@ -563,7 +564,8 @@ struct hipmr_server {
             int grid = std::max(1, std::min(cfg.blocks_per_cu * cus, (total + 3) / 4));
             void* a1[4] = {&s.dev_desc, (void*)&nj, &total, &s.tpart};
             if (e == hipSuccess)
-                e = hipModuleLaunchKernel(f_s1, grid, 1, 1, kServeBlock, 1, 1, 0, s.stream, a1, nullptr);
+                e = hipModuleLaunchKernel(f_s1, grid, 1, 1, kServeBlock, 1, 1, (unsigned)nj * 4, s.stream,
+                                          a1, nullptr);
             void* a2[6] = {&s.dev_desc, (void*)&nj, &total, &s.tpart, &s.dev_flags, &s.seq};
             if (e == hipSuccess)
                 e = hipModuleLaunchKernel(f_s2, nj, 1, 1, kFinBlock, 1, 1, 0, s.stream, a2, nullptr);
