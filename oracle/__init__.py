@@ -15,6 +15,9 @@ Generation with PyCUDA"):
   folded by a reduce expression in ``a`` and ``b`` from a neutral element, the
   result being a single value of the dtype named first (section
   "Map-Reduce");
+* ``scan``: the parallel prefix sums the paper lists among the further
+  facilities -- every prefix of the map values folded from the neutral
+  element, inclusive or exclusive (section "Further Facilities");
 * decoders for the 16- and 8-bit float formats used by the precision
   extension, an exact sum and a norm.
 
@@ -28,8 +31,9 @@ from .api import CSyntaxError, Lanes, OracleError, elementwise, map_chunks, map_
 from .ctype import parse_signature, round_fraction, f32_literal
 from .formats import decode_bf16, decode_e4m3fn, decode_f16
 from .reduce import ReduceResult, canonical_op, eval_neutral, exact_sum, norm2, reduce
+from .scan import ScanResult, scan
 
-__all__ = ["elementwise", "map_values", "map_chunks", "reduce", "ReduceResult",
+__all__ = ["elementwise", "map_values", "map_chunks", "reduce", "ReduceResult", "scan", "ScanResult",
            "canonical_op", "eval_neutral", "exact_sum", "norm2", "parse_signature",
            "round_fraction", "f32_literal", "decode_bf16", "decode_f16", "decode_e4m3fn",
            "Lanes", "OracleError", "CSyntaxError"]
