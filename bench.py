@@ -42,8 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="precision,batched,served",
-                   help="comma list of the extension measurements to run")
+    p.add_argument("--extensions", default="precision,batched,served,scan",
+                   help="comma list of the extension measurements to run "
+                        "(precision, batched, served, scan)")
     p.add_argument("--serving-duration", type=float, default=5.0,
                    help="measured seconds of each serving rate (after 1 s of warm-up)")
     p.add_argument("--cpu-sample", type=int, default=1 << 27,
@@ -147,6 +148,32 @@ def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
         torch.cuda.empty_cache()
     return {"n": n, "workload": "lognormal(0,3) x random sign, per-tensor power-of-two scale",
             "bytes_note": "sum reads n*size once; the scaled norm reads it twice", "formats": out}
+
+
+def bench_scan(torch, hm, workloads, dev, stream, reps=10):
+    """Prefix scans at n = 2^28 (the plain workload's arrays): inclusive float
+    sum of x (4 B read twice + 4 B written = 12 B/element) and inclusive
+    int64 sum of the int32 k (4 + 4 + 8 = 16 B/element)."""
+    n = workloads.N_PLAIN
+    x, _ = workloads.plain_xy(n)
+    xd = torch.from_numpy(x).to(dev)
+    kd = torch.from_numpy(workloads.plain_k(n)).to(dev)
+    res = {"n": n}
+    for name, expr, sig, src, out_dt, per in (
+            ("sum_f32", "x[i]", "float: const float *x", xd, torch.float32, 12),
+            ("sum_i32_to_i64", "k[i]", "long: const int *k", kd, torch.int64, 16)):
+        k = hm.compile(expr, sig, name=f"scan_{name}")
+        out = torch.empty(n, dtype=out_dt, device=dev)
+        ws = hm.hipmr.workspace(hm.scan_workspace_bytes(k, n), dev, stream.cuda_stream)
+        ms = _time_ms(torch, lambda: hm.scan(k, "a+b", "0", n, [src], out, workspace_buf=ws), reps, stream)
+        gbs = per * n / ms / 1e6
+        res[name] = {"ms": round(ms, 4), "bytes_per_element": per, "GB/s": round(gbs, 1),
+                     "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "elements_per_s": round(n / ms * 1e3, 1), "symbols": k.last_symbols()}
+        del out
+    del xd, kd
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
@@ -431,6 +458,9 @@ def main():
     if "batched" in ext:
         line["batched"] = bench_batched(torch, hm, workloads, dev)
         print("batched done", file=sys.stderr, flush=True)
+    if "scan" in ext:
+        line["scan"] = bench_scan(torch, hm, workloads, dev, stream)
+        print("scan done", file=sys.stderr, flush=True)
     if "served" in ext:
         line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration)
     if not args.no_cpu_baseline:

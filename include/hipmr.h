@@ -233,6 +233,35 @@ hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void *const *args, double po
                          int32_t passes, void *out, void *workspace, size_t workspace_bytes,
                          const hipmr_launch_config *cfg, void *stream);
 
+/* ------------------------------------------------------------------ prefix scan */
+
+/* Bytes of device workspace hipmr_scan needs (two tables of at most 16384
+ * wave totals of the result type); 0 for an elementwise or invalid handle. */
+size_t hipmr_scan_workspace_bytes(hipmr_handle h, int64_t n);
+
+/* Prefix scan of a map: the parallel prefix sums of section "Further
+ * Facilities", over the map, combine and neutral element of section
+ * "Map-Reduce":
+ *   inclusive (exclusive == 0): out[i] = neutral (+) map(0) (+) ... (+) map(i)
+ *   exclusive (exclusive == 1): out[i] = neutral (+) map(0) (+) ... (+) map(i-1)
+ *   h:          map-reduce handle ("T: ..."); map_expr is the handle's.
+ *   combine_op, neutral: as for hipmr_reduce (associative and commutative).
+ *   out:        device array of n values of the result type T; must not
+ *               overlap the inputs.
+ *   workspace:  at least hipmr_scan_workspace_bytes(h, n) bytes (caller-owned).
+ *   cfg:        NULL or a geometry (block, items_per_thread, vec, flags).
+ * Three launches on `stream`: every wave folds a contiguous range, one block
+ * scans the wave totals, every wave rescans its range from its prefix.  The
+ * order of combination depends only on n, alignment and geometry (bitwise
+ * repeatable).  16-byte accesses when every array and out share one
+ * alignment and the map reads arrays only as name[i]; one element at a time
+ * otherwise.  n == 0 writes nothing.  Errors: E_INVALID (NULL, exclusive not
+ * 0/1), E_MISMATCH (elementwise handle), E_WORKSPACE, E_PARSE / E_COMPILE
+ * (combine or neutral), E_HIP. */
+hipmr_status hipmr_scan(hipmr_handle h, const char *combine_op, const char *neutral, int64_t n,
+                        void *const *args, void *out, int32_t exclusive, void *workspace,
+                        size_t workspace_bytes, const hipmr_launch_config *cfg, void *stream);
+
 /* ------------------------------------------------------------------ batching extension */
 
 /* Bytes of device workspace hipmr_reduce_segmented / hipmr_autotune_segmented

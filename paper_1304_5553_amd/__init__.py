@@ -9,7 +9,7 @@ memory and streams only.
 """
 
 from .hipmr import (JOB_NAMES, CFG_FORCE_SCALAR, Graph, Server, autotune_reduce, autotune_segmented,
-                    reduce_segmented, segmented_workspace_bytes, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
+                    reduce_segmented, segmented_workspace_bytes, scan, scan_workspace_bytes, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
                     ElementwiseKernel, HipError, HipmrError, InvalidError, Kernel, LaunchConfig,
                     MismatchError, ParseError, ReductionKernel, UnsupportedError, WorkspaceError,
                     cache_drop_memory, cache_stats, compile, elementwise, lib, prepare_reduce,
@@ -17,7 +17,8 @@ from .hipmr import (JOB_NAMES, CFG_FORCE_SCALAR, Graph, Server, autotune_reduce,
                     sha256_hex, torch_dtype)
 
 __all__ = ["ElementwiseKernel", "ReductionKernel", "Kernel", "compile", "elementwise", "reduce",
-           "reduce_compensated", "norm2", "reduce_segmented", "segmented_workspace_bytes",
+           "reduce_compensated", "norm2", "reduce_segmented", "segmented_workspace_bytes", "scan",
+           "scan_workspace_bytes",
            "autotune_segmented", "autotune_reduce", "Graph", "Server", "JOB_NAMES",
            "prepare_reduce", "reduce_workspace_bytes", "cache_stats", "cache_drop_memory",
            "sha256_hex", "selftest_compile", "lib", "torch_dtype", "LaunchConfig",

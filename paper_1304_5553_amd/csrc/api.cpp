@@ -680,6 +680,24 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
                     if (st != HIPMR_OK) break;
                 }
             }
+            if (st == HIPMR_OK) {
+                // prefix scan: wave totals, their scan, the rescan (vector and scalar)
+                for (KernelKind k : {KernelKind::ScanUpVector, KernelKind::ScanUpScalar, KernelKind::ScanMid,
+                                     KernelKind::ScanDownVector, KernelKind::ScanDownScalar}) {
+                    const bool vk = k == KernelKind::ScanUpVector || k == KernelKind::ScanDownVector;
+                    if (vk && !h->prog.info.vectorizable) continue;
+                    KernelSpec q;
+                    q.kind = k;
+                    q.block = k == KernelKind::ScanMid ? 1024 : 256;
+                    q.ipt = k == KernelKind::ScanMid ? 1 : 4;
+                    q.vec = vk ? h->default_vec : 1;
+                    q.combine = c.combine;
+                    q.neutral = c.neutral;
+                    st = get_variant(h, q, &co);
+                    if (st != HIPMR_OK) break;
+                    ++built;
+                }
+            }
             if (st == HIPMR_OK && h->prog.sig.result == DT_F32) {
                 // precision extension: compensated sum, norm passes, finishers
                 std::vector<KernelSpec> specs;

@@ -917,6 +917,215 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
+// ------------------------------------------------------------ prefix scan
+// Reduce-then-scan over a fixed partition: wave w owns the elements
+// [head + w C, head + (w + 1) C) (wave 0 also the unaligned head [0, head)),
+// C = P passes x U sub-tiles x 64 lanes x V elements; lane l owns the V
+// consecutive elements at 64 V u + V l of each sub-tile.  Pass 1 folds each
+// wave's range; pass 2 (one block) scans the wave totals; pass 3 rescans each
+// range from its wave prefix.  The order of every combination is a fixed
+// function of n and the geometry.
+const char* kScanHelpers = R"HIP(
+// inclusive scan across the wave (lane l receives v_0 (+) ... (+) v_l)
+__device__ __forceinline__ hipmr_acc hipmr_wave_scan(hipmr_acc v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const hipmr_acc y = __shfl_up(v, d, 64);
+    if (lane >= d) v = hipmr_combine(y, v);
+  }
+  return v;
+}
+)HIP";
+
+const char* kScanUp = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head, int hipmr_passes,
+          long long hipmr_waves, hipmr_acc* __restrict__ hipmr_partial)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  const int hipmr_lane = threadIdx.x & 63;
+  const long long hipmr_w = (long long)blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6);
+  if (hipmr_w >= hipmr_waves) return;           // whole waves; no block barrier below
+  const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
+  const long long hipmr_sub = 64LL * HIPMR_V;
+  const long long hipmr_c = hipmr_sub * HIPMR_U * hipmr_passes;
+  const long long hipmr_b0 = hipmr_h + hipmr_w * hipmr_c;
+  const long long hipmr_e = hipmr_b0 + hipmr_c < hipmr_n ? hipmr_b0 + hipmr_c : hipmr_n;
+  hipmr_acc hipmr_a[HIPMR_U];
+#pragma unroll
+  for (int u = 0; u < HIPMR_U; ++u) hipmr_a[u] = hipmr_neutral;
+  if (hipmr_w == 0 && hipmr_lane < hipmr_h) {
+    const hipmr_idx i = (hipmr_idx)hipmr_lane;
+    hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
+  }
+  for (int hipmr_p = 0; hipmr_p < hipmr_passes; ++hipmr_p) {
+    const long long hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
+    if (hipmr_pb >= hipmr_e) break;
+    @@DECL_PACKS@@
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+      if (hipmr_off + HIPMR_V <= hipmr_e) {
+        @@LOADS@@
+      }
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+      if (hipmr_off + HIPMR_V <= hipmr_e) {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@VMAP@@));
+        }
+      } else {
+        for (long long hipmr_k = hipmr_off; hipmr_k < hipmr_e; ++hipmr_k) {
+          const hipmr_idx i = (hipmr_idx)hipmr_k;
+          hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@MAP@@));
+        }
+      }
+    }
+  }
+  hipmr_acc hipmr_r = hipmr_fold<HIPMR_U>(hipmr_a);
+  hipmr_r = hipmr_block_reduce<64>(hipmr_r, hipmr_neutral);
+  if (hipmr_lane == 0) hipmr_partial[hipmr_w] = hipmr_r;
+}
+)HIP";
+
+// Pass 2: exclusive scan of the wave totals by one block of 1024 threads;
+// thread t takes a contiguous run of them.
+const char* kScanMid = R"HIP(
+extern "C" __global__ void __launch_bounds__(1024)
+@@KNAME@@(const hipmr_acc* __restrict__ hipmr_partial, long long hipmr_waves,
+          hipmr_acc* __restrict__ hipmr_prefix)
+{
+  constexpr int B = 1024, W = B / 64;
+  __shared__ hipmr_acc hipmr_wt[W];
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long long per = (hipmr_waves + B - 1) / B;
+  const long long t0 = (long long)threadIdx.x * per;
+  const long long t1 = t0 + per < hipmr_waves ? t0 + per : hipmr_waves;
+  hipmr_acc tot = hipmr_neutral;
+  for (long long k = t0; k < t1; ++k) tot = hipmr_combine(tot, hipmr_partial[k]);
+  const hipmr_acc x = hipmr_wave_scan(tot, lane);
+  if (lane == 63) hipmr_wt[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    hipmr_acc v = lane < W ? hipmr_wt[lane] : hipmr_neutral;
+    v = hipmr_wave_scan(v, lane);
+    if (lane < W) hipmr_wt[lane] = v;
+  }
+  __syncthreads();
+  const hipmr_acc up = __shfl_up(x, 1, 64);
+  hipmr_acc run = lane == 0 ? hipmr_neutral : up;
+  if (w > 0) run = hipmr_combine(hipmr_wt[w - 1], run);
+  for (long long k = t0; k < t1; ++k) {
+    hipmr_prefix[k] = run;
+    run = hipmr_combine(run, hipmr_partial[k]);
+  }
+}
+)HIP";
+
+// Pass 3: each wave rescans its range from its prefix and writes the outputs.
+const char* kScanDown = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head, int hipmr_passes,
+          long long hipmr_waves, const hipmr_acc* __restrict__ hipmr_prefix,
+          hipmr_acc* __restrict__ hipmr_out, int hipmr_exclusive)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  const int hipmr_lane = threadIdx.x & 63;
+  const long long hipmr_w = (long long)blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6);
+  if (hipmr_w >= hipmr_waves) return;           // whole waves; no block barrier below
+  const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
+  const long long hipmr_sub = 64LL * HIPMR_V;
+  const long long hipmr_c = hipmr_sub * HIPMR_U * hipmr_passes;
+  const long long hipmr_b0 = hipmr_h + hipmr_w * hipmr_c;
+  const long long hipmr_e = hipmr_b0 + hipmr_c < hipmr_n ? hipmr_b0 + hipmr_c : hipmr_n;
+  hipmr_acc hipmr_carry = hipmr_prefix[hipmr_w];
+  if (hipmr_w == 0 && hipmr_h > 0) {            // the unaligned head, one element per lane
+    hipmr_acc hipmr_v = hipmr_neutral;
+    if (hipmr_lane < hipmr_h) {
+      const hipmr_idx i = (hipmr_idx)hipmr_lane;
+      hipmr_v = (hipmr_acc)(@@MAP@@);
+    }
+    const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_v, hipmr_lane);
+    const hipmr_acc hipmr_up = __shfl_up(hipmr_x, 1, 64);
+    if (hipmr_lane < hipmr_h)
+      hipmr_out[hipmr_lane] = hipmr_exclusive ? (hipmr_lane == 0 ? hipmr_carry : hipmr_combine(hipmr_carry, hipmr_up))
+                                              : hipmr_combine(hipmr_carry, hipmr_x);
+    hipmr_carry = hipmr_combine(hipmr_carry, __shfl(hipmr_x, 63, 64));
+  }
+  for (int hipmr_p = 0; hipmr_p < hipmr_passes; ++hipmr_p) {
+    const long long hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
+    if (hipmr_pb >= hipmr_e) break;
+    @@DECL_PACKS@@
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+      if (hipmr_off + HIPMR_V <= hipmr_e) {
+        @@LOADS@@
+      }
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+      const bool hipmr_full = hipmr_off + HIPMR_V <= hipmr_e;
+      hipmr_pack<hipmr_acc, HIPMR_V> hipmr_t;   // the lane's inclusive prefixes
+      if (hipmr_full) {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          const hipmr_acc hipmr_m = (hipmr_acc)(@@VMAP@@);
+          hipmr_t.v[hipmr_j] = hipmr_j == 0 ? hipmr_m : hipmr_combine(hipmr_t.v[hipmr_j - 1], hipmr_m);
+        }
+      } else {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          hipmr_acc hipmr_m = hipmr_neutral;
+          if (hipmr_off + hipmr_j < hipmr_e) {
+            const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+            hipmr_m = (hipmr_acc)(@@MAP@@);
+          }
+          hipmr_t.v[hipmr_j] = hipmr_j == 0 ? hipmr_m : hipmr_combine(hipmr_t.v[hipmr_j - 1], hipmr_m);
+        }
+      }
+      const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_t.v[HIPMR_V - 1], hipmr_lane);
+      const hipmr_acc hipmr_up = __shfl_up(hipmr_x, 1, 64);
+      const hipmr_acc hipmr_pre = hipmr_lane == 0 ? hipmr_carry : hipmr_combine(hipmr_carry, hipmr_up);
+      hipmr_pack<hipmr_acc, HIPMR_V> hipmr_o;
+      if (hipmr_exclusive) {
+        hipmr_o.v[0] = hipmr_pre;
+#pragma unroll
+        for (int hipmr_j = 1; hipmr_j < HIPMR_V; ++hipmr_j)
+          hipmr_o.v[hipmr_j] = hipmr_combine(hipmr_pre, hipmr_t.v[hipmr_j - 1]);
+      } else {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j)
+          hipmr_o.v[hipmr_j] = hipmr_combine(hipmr_pre, hipmr_t.v[hipmr_j]);
+      }
+      if (hipmr_full) {
+        hipmr_store<HIPMR_NTS>(hipmr_out + hipmr_off, hipmr_o);
+      } else {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j)
+          if (hipmr_off + hipmr_j < hipmr_e) hipmr_out[hipmr_off + hipmr_j] = hipmr_o.v[hipmr_j];
+      }
+      hipmr_carry = hipmr_combine(hipmr_carry, __shfl(hipmr_x, 63, 64));
+    }
+  }
+}
+)HIP";
+
 void replace_all(std::string& s, const std::string& key, const std::string& val) {
     size_t pos = 0;
     while ((pos = s.find(key, pos)) != std::string::npos) {
@@ -966,7 +1175,17 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
         case KernelKind::SegPlan: tmpl = kSegPlan; tag = "segplan"; break;
         case KernelKind::SegS1: tmpl = kSegS1; tag = "seg1"; reduce = true; break;
         case KernelKind::SegS2: tmpl = kSegS2; tag = "seg2"; reduce = true; break;
+        case KernelKind::ScanUpVector: tmpl = kScanUp; tag = "scu"; reduce = true; break;
+        case KernelKind::ScanUpScalar: tmpl = kScanUp; tag = "scus"; reduce = true; break;
+        case KernelKind::ScanMid: tmpl = kScanMid; tag = "scm"; reduce = true; break;
+        case KernelKind::ScanDownVector: tmpl = kScanDown; tag = "scd"; reduce = true; break;
+        case KernelKind::ScanDownScalar: tmpl = kScanDown; tag = "scds"; reduce = true; break;
     }
+    const bool scan = spec.kind == KernelKind::ScanUpVector || spec.kind == KernelKind::ScanUpScalar ||
+                      spec.kind == KernelKind::ScanMid || spec.kind == KernelKind::ScanDownVector ||
+                      spec.kind == KernelKind::ScanDownScalar;
+    // scalar scan kinds: one-element chunks read through the expression itself
+    const bool scan_scalar = spec.kind == KernelKind::ScanUpScalar || spec.kind == KernelKind::ScanDownScalar;
     const bool seg = spec.kind == KernelKind::SegPlan || spec.kind == KernelKind::SegS1;
     const bool amax = spec.kind == KernelKind::AmaxS1Vector || spec.kind == KernelKind::AmaxS1Scalar;
     std::string body = tmpl;
@@ -1000,7 +1219,11 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     }
 
     std::string scalar_text = join_tokens(prog.toks);
-    std::string vector_text = vectorize_accesses(prog.toks, prog.sig);
+    std::string vector_text = scan_scalar ? scalar_text : vectorize_accesses(prog.toks, prog.sig);
+    if (scan_scalar) {
+        decl_packs.clear();
+        loads.clear();
+    }
 
     replace_all(body, "@@PARAMS@@", params);
     replace_all(body, "@@DECL_PACKS@@", decl_packs);
@@ -1042,6 +1265,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     }
     if (comp) src << kCompHelpers;
     if (seg) src << kSegHelpers;
+    if (scan) src << kScanHelpers;
     // the symbol carries a hash of everything that shapes the kernel
     std::string unnamed = cbody + "\n" + body;
     std::string key = sha256_hex(unnamed.data(), unnamed.size());

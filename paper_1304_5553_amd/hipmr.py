@@ -113,6 +113,9 @@ _SIGS = {
                                ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_prepare_reduce": (_I32, [_VP, _CP, _CP]),
     "hipmr_prepare_reduce_ex": (_I32, [_VP, _CP, _CP, ctypes.POINTER(LaunchConfig)]),
+    "hipmr_scan_workspace_bytes": (_SZ, [_VP, _I64]),
+    "hipmr_scan": (_I32, [_VP, _CP, _CP, _I64, _VP, _VP, _I32, _VP, _SZ,
+                          ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_segmented_workspace_bytes": (_SZ, [_VP, _I32, _I64]),
     "hipmr_reduce_segmented": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ,
                                       ctypes.POINTER(LaunchConfig), _VP]),
@@ -383,6 +386,25 @@ def norm2(handle: Kernel, n, args, post_scale=1.0, passes=2, out=None, workspace
                              ctypes.c_void_p(out.data_ptr()),
                              ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
                              _config(config), s))
+    return out
+
+
+def scan_workspace_bytes(handle: Kernel, n):
+    return lib().hipmr_scan_workspace_bytes(handle.handle, int(n))
+
+
+def scan(handle: Kernel, combine_op, neutral, n, args, out, exclusive=False, workspace_buf=None,
+         stream=None, config=None):
+    """out[i] = neutral (+) map(0) (+) ... (+) map(i) (inclusive) or up to
+    map(i - 1) (exclusive); `out` is a device tensor of n result values."""
+    s = _stream_ptr(stream)
+    if workspace_buf is None:
+        workspace_buf = workspace(scan_workspace_bytes(handle, n), out.device, s)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_scan(handle.handle, combine_op.encode(), neutral.encode(), int(n), ptrs,
+                            ctypes.c_void_p(out.data_ptr()), 1 if exclusive else 0,
+                            ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
+                            _config(config), s))
     return out
 
 
