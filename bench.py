@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--extensions", default="precision,batched,served,scan",
                    help="comma list of the extension measurements to run "
                         "(precision, batched, served, scan)")
+    p.add_argument("--serving-rates", default="",
+                   help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
                    help="measured seconds of each serving rate (after 1 s of warm-up)")
     p.add_argument("--cpu-sample", type=int, default=1 << 27,
@@ -462,7 +464,9 @@ def main():
         line["scan"] = bench_scan(torch, hm, workloads, dev, stream)
         print("scan done", file=sys.stderr, flush=True)
     if "served" in ext:
-        line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration)
+        rates = tuple(int(r) for r in args.serving_rates.split(",") if r.strip()) or None
+        line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration,
+                                       rates=rates)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, k, args.cpu_sample)
     print(json.dumps(line), flush=True)

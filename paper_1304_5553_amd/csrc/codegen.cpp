@@ -997,21 +997,27 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 )HIP";
 
 // Pass 2: exclusive scan of the wave totals by one block of 1024 threads;
-// thread t takes a contiguous run of them.
+// thread t takes a contiguous run of at most 16 of them (all loaded before
+// any is combined).
 const char* kScanMid = R"HIP(
 extern "C" __global__ void __launch_bounds__(1024)
 @@KNAME@@(const hipmr_acc* __restrict__ hipmr_partial, long long hipmr_waves,
           hipmr_acc* __restrict__ hipmr_prefix)
 {
-  constexpr int B = 1024, W = B / 64;
+  constexpr int B = 1024, W = B / 64, R = 16;
   __shared__ hipmr_acc hipmr_wt[W];
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long long per = (hipmr_waves + B - 1) / B;
+  const long long per = (hipmr_waves + B - 1) / B;          // <= R (at most 16384 waves)
   const long long t0 = (long long)threadIdx.x * per;
-  const long long t1 = t0 + per < hipmr_waves ? t0 + per : hipmr_waves;
+  hipmr_acc v[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    v[k] = k < per && t0 + k < hipmr_waves ? hipmr_partial[t0 + k] : hipmr_neutral;
   hipmr_acc tot = hipmr_neutral;
-  for (long long k = t0; k < t1; ++k) tot = hipmr_combine(tot, hipmr_partial[k]);
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    if (k < per && t0 + k < hipmr_waves) tot = hipmr_combine(tot, v[k]);
   const hipmr_acc x = hipmr_wave_scan(tot, lane);
   if (lane == 63) hipmr_wt[w] = x;
   __syncthreads();
@@ -1024,14 +1030,19 @@ extern "C" __global__ void __launch_bounds__(1024)
   const hipmr_acc up = __shfl_up(x, 1, 64);
   hipmr_acc run = lane == 0 ? hipmr_neutral : up;
   if (w > 0) run = hipmr_combine(hipmr_wt[w - 1], run);
-  for (long long k = t0; k < t1; ++k) {
-    hipmr_prefix[k] = run;
-    run = hipmr_combine(run, hipmr_partial[k]);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (k < per && t0 + k < hipmr_waves) {
+      hipmr_prefix[t0 + k] = run;
+      run = hipmr_combine(run, v[k]);
+    }
   }
 }
 )HIP";
 
 // Pass 3: each wave rescans its range from its prefix and writes the outputs.
+// Two register sets of chunks alternate between passes, so the loads of the
+// next pass are in flight while the current pass is scanned and stored.
 const char* kScanDown = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head, int hipmr_passes,
@@ -1065,17 +1076,51 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
                                               : hipmr_combine(hipmr_carry, hipmr_x);
     hipmr_carry = hipmr_combine(hipmr_carry, __shfl(hipmr_x, 63, 64));
   }
-  for (int hipmr_p = 0; hipmr_p < hipmr_passes; ++hipmr_p) {
-    const long long hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
-    if (hipmr_pb >= hipmr_e) break;
-    @@DECL_PACKS@@
+  @@DECL_PACKS@@
+  @@DECL_PACKS_Q@@
+  long long hipmr_pb = hipmr_b0;
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
-      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
-      if (hipmr_off + HIPMR_V <= hipmr_e) {
-        @@LOADS@@
+  for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+    const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+    if (hipmr_off + HIPMR_V <= hipmr_e) {
+      @@LOADS@@
+    }
+  }
+  for (int hipmr_p = 0; hipmr_p < hipmr_passes; hipmr_p += 2) {
+    hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
+    if (hipmr_pb >= hipmr_e) break;
+    {
+      const long long hipmr_nb = hipmr_pb + hipmr_sub * HIPMR_U;     // prefetch the next pass
+#pragma unroll
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_nb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+        if (hipmr_off + HIPMR_V <= hipmr_e) {
+          @@LOADS_Q@@
+        }
       }
     }
+    @@PASS_P@@
+    hipmr_pb += hipmr_sub * HIPMR_U;
+    if (hipmr_pb >= hipmr_e) break;
+    {
+      const long long hipmr_nb = hipmr_pb + hipmr_sub * HIPMR_U;
+#pragma unroll
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_nb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+        if (hipmr_off + HIPMR_V <= hipmr_e) {
+          @@LOADS@@
+        }
+      }
+    }
+    @@PASS_Q@@
+  }
+}
+)HIP";
+
+// One pass of pass 3 over the chunks of one register set (@@VMAPX@@ reads
+// them): per sub-tile, the lane's inclusive prefixes of its V elements, a
+// wave scan of the lane totals, the outputs, the carry.
+const char* kScanDownPass = R"HIP(
 #pragma unroll
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
       const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
@@ -1085,7 +1130,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 #pragma unroll
         for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
           const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
-          const hipmr_acc hipmr_m = (hipmr_acc)(@@VMAP@@);
+          const hipmr_acc hipmr_m = (hipmr_acc)(@@VMAPX@@);
           hipmr_t.v[hipmr_j] = hipmr_j == 0 ? hipmr_m : hipmr_combine(hipmr_t.v[hipmr_j - 1], hipmr_m);
         }
       } else {
@@ -1122,8 +1167,6 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       }
       hipmr_carry = hipmr_combine(hipmr_carry, __shfl(hipmr_x, 63, 64));
     }
-  }
-}
 )HIP";
 
 void replace_all(std::string& s, const std::string& key, const std::string& val) {
@@ -1223,6 +1266,17 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     if (scan_scalar) {
         decl_packs.clear();
         loads.clear();
+    }
+    if (spec.kind == KernelKind::ScanDownVector || spec.kind == KernelKind::ScanDownScalar) {
+        // the second register set of chunks (prefetch of the next pass)
+        auto q = [](std::string t) { replace_all(t, "hipmr_p_", "hipmr_q_"); return t; };
+        std::string pass_p = kScanDownPass, pass_q = kScanDownPass;
+        replace_all(pass_p, "@@VMAPX@@", vector_text);
+        replace_all(pass_q, "@@VMAPX@@", q(vector_text));
+        replace_all(body, "@@PASS_P@@", pass_p);
+        replace_all(body, "@@PASS_Q@@", pass_q);
+        replace_all(body, "@@DECL_PACKS_Q@@", q(decl_packs));
+        replace_all(body, "@@LOADS_Q@@", q(loads));
     }
 
     replace_all(body, "@@PARAMS@@", params);
