@@ -926,14 +926,45 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 // range from its wave prefix.  The order of every combination is a fixed
 // function of n and the geometry.
 const char* kScanHelpers = R"HIP(
-// inclusive scan across the wave (lane l receives v_0 (+) ... (+) v_l)
-__device__ __forceinline__ hipmr_acc hipmr_wave_scan(hipmr_acc v, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const hipmr_acc y = __shfl_up(v, d, 64);
-    if (lane >= d) v = hipmr_combine(y, v);
+// Data-parallel-primitive (DPP) lane moves on 32-bit halves: lanes whose
+// source lies outside the pattern (or whose row is masked off) receive
+// `fill`.
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T hipmr_dpp(T v, T fill) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, fill), __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+  } else {
+    const unsigned long long a = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long f = __builtin_bit_cast(unsigned long long, fill);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)a, CTRL, ROWS, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(a >> 32),
+                                                              CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
   }
-  return v;
+}
+
+// inclusive scan across the wave (lane l receives v_0 (+) ... (+) v_l):
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the totals of
+// row 0 / rows 0-1 broadcast into the rows after them
+template <typename T>
+__device__ __forceinline__ T hipmr_wave_scan(T v, int lane, T e) {
+  if constexpr (sizeof(T) == 4 || sizeof(T) == 8) {
+    v = hipmr_combine(hipmr_dpp<0x111, 0xf>(v, e), v);     // row_shr:1
+    v = hipmr_combine(hipmr_dpp<0x112, 0xf>(v, e), v);     // row_shr:2
+    v = hipmr_combine(hipmr_dpp<0x114, 0xf>(v, e), v);     // row_shr:4
+    v = hipmr_combine(hipmr_dpp<0x118, 0xf>(v, e), v);     // row_shr:8
+    v = hipmr_combine(hipmr_dpp<0x142, 0xa>(v, e), v);     // row_bcast:15 into rows 1, 3
+    v = hipmr_combine(hipmr_dpp<0x143, 0xc>(v, e), v);     // row_bcast:31 into rows 2, 3
+    return v;
+  } else {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const T y = __shfl_up(v, d, 64);
+      if (lane >= d) v = hipmr_combine(y, v);
+    }
+    return v;
+  }
 }
 )HIP";
 
@@ -1018,12 +1049,12 @@ extern "C" __global__ void __launch_bounds__(1024)
 #pragma unroll
   for (int k = 0; k < R; ++k)
     if (k < per && t0 + k < hipmr_waves) tot = hipmr_combine(tot, v[k]);
-  const hipmr_acc x = hipmr_wave_scan(tot, lane);
+  const hipmr_acc x = hipmr_wave_scan(tot, lane, hipmr_neutral);
   if (lane == 63) hipmr_wt[w] = x;
   __syncthreads();
   if (w == 0) {
     hipmr_acc v = lane < W ? hipmr_wt[lane] : hipmr_neutral;
-    v = hipmr_wave_scan(v, lane);
+    v = hipmr_wave_scan(v, lane, hipmr_neutral);
     if (lane < W) hipmr_wt[lane] = v;
   }
   __syncthreads();
@@ -1069,7 +1100,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       const hipmr_idx i = (hipmr_idx)hipmr_lane;
       hipmr_v = (hipmr_acc)(@@MAP@@);
     }
-    const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_v, hipmr_lane);
+    const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_v, hipmr_lane, hipmr_neutral);
     const hipmr_acc hipmr_up = __shfl_up(hipmr_x, 1, 64);
     if (hipmr_lane < hipmr_h)
       hipmr_out[hipmr_lane] = hipmr_exclusive ? (hipmr_lane == 0 ? hipmr_carry : hipmr_combine(hipmr_carry, hipmr_up))
@@ -1144,7 +1175,7 @@ const char* kScanDownPass = R"HIP(
           hipmr_t.v[hipmr_j] = hipmr_j == 0 ? hipmr_m : hipmr_combine(hipmr_t.v[hipmr_j - 1], hipmr_m);
         }
       }
-      const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_t.v[HIPMR_V - 1], hipmr_lane);
+      const hipmr_acc hipmr_x = hipmr_wave_scan(hipmr_t.v[HIPMR_V - 1], hipmr_lane, hipmr_neutral);
       const hipmr_acc hipmr_up = __shfl_up(hipmr_x, 1, 64);
       const hipmr_acc hipmr_pre = hipmr_lane == 0 ? hipmr_carry : hipmr_combine(hipmr_carry, hipmr_up);
       hipmr_pack<hipmr_acc, HIPMR_V> hipmr_o;
