@@ -17,7 +17,7 @@ namespace hipmr {
 int default_vec_for(const Signature& sig) {
     int min_size = 0;
     for (auto& a : sig.args)
-        if (a.pointer && (a.read || a.written)) {
+        if (chunked(a)) {
             int s = dtype_size(a.dtype);
             if (min_size == 0 || s < min_size) min_size = s;
         }
@@ -115,7 +115,7 @@ long long common_head(const hipmr_kernel* h, void* const* args, int vec) {
         bool ok = true;
         for (size_t k = 0; k < h->prog.sig.args.size() && ok; ++k) {
             const ArgDecl& a = h->prog.sig.args[k];
-            if (!a.pointer || !(a.read || a.written)) continue;
+            if (!chunked(a)) continue;
             uintptr_t p = (uintptr_t)(*(void* const*)args[k]);
             int s = dtype_size(a.dtype);
             uintptr_t align = (uintptr_t)std::min(vec * s, 16);

@@ -1280,7 +1280,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
 
     std::string decl_packs, loads, stores;
     for (const ArgDecl& a : prog.sig.args) {
-        if (!a.pointer || !(a.read || a.written)) continue;
+        if (!chunked(a)) continue;
         if (a.dtype == DT_FP8 && !a.written && spec.vec >= 4)
             decl_packs += "hipmr_pack_fp8ro<HIPMR_V> hipmr_p_" + a.name + "[HIPMR_U]; ";
         else

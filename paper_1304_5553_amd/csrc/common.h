@@ -43,7 +43,13 @@ struct ArgDecl {
     bool read = false;        // the expression reads name[...] (or the scalar)
     bool written = false;     // the expression assigns name[i]
     bool write_only = false;  // written unconditionally before any read: no load needed
+    bool lane = false;        // accessed as name[i]
+    bool uniform = false;     // read as name[<integer literal>] (the same element for every i)
 };
+
+// An array the vector kernels move in 16-byte chunks (accessed as name[i] or
+// written); arrays read only at constant indices are read directly instead.
+inline bool chunked(const ArgDecl& a) { return a.pointer && (a.lane || a.written); }
 
 struct Signature {
     bool is_reduce = false;
@@ -63,7 +69,7 @@ struct Token {
 hipmr_status lex(const std::string& src, std::vector<Token>* out);
 
 struct ExprInfo {
-    bool vectorizable = true;   // every array reference is exactly name[i]
+    bool vectorizable = true;   // every array reference is name[i] or a read of a fixed element
     bool has_writes = false;
 };
 

@@ -270,6 +270,7 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
     std::map<std::string, size_t> arg_index;
     for (size_t a = 0; a < sig->args.size(); ++a) {
         sig->args[a].read = sig->args[a].written = sig->args[a].write_only = false;
+        sig->args[a].lane = sig->args[a].uniform = false;
         arg_index[sig->args[a].name] = a;
     }
     // balance of brackets; forbidden constructs
@@ -324,9 +325,16 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         bool lane_local = k + 3 < toks.size() && is_punct(toks[k + 1], "[") &&
                           toks[k + 2].kind == Token::Ident && toks[k + 2].text == "i" &&
                           is_punct(toks[k + 3], "]");
+        // a read of one fixed element (name[3]): uniform across i, read directly
+        bool constant_index = !lane_local && k + 3 < toks.size() && is_punct(toks[k + 1], "[") &&
+                              toks[k + 2].kind == Token::Number && is_punct(toks[k + 3], "]");
         size_t after;   // token after the closing ']'
         if (lane_local) {
             after = k + 4;
+            a.lane = true;
+        } else if (constant_index) {
+            after = k + 4;
+            a.uniform = true;
         } else {
             out->vectorizable = false;
             if (!(k + 1 < toks.size() && is_punct(toks[k + 1], "["))) {
@@ -362,6 +370,9 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         ArgDecl& d = sig->args[a];
         d.write_only = d.pointer && d.written && !d.read && uncond_write[a];
         if (d.written) out->has_writes = true;
+        // a fixed element of an array the expression also writes could be
+        // written by another i: keep such expressions on the one-element path
+        if (d.uniform && d.written) out->vectorizable = false;
     }
     if (is_map && out->has_writes)
         return fail(HIPMR_E_UNSUPPORTED, "expression: a map expression may not assign to arrays");

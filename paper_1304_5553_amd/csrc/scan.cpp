@@ -35,7 +35,7 @@ long long scan_head(const hipmr_kernel* h, void* const* args, const void* out, i
         bool ok = true;
         for (size_t k = 0; k < h->prog.sig.args.size() && ok; ++k) {
             const ArgDecl& a = h->prog.sig.args[k];
-            if (!a.pointer || !(a.read || a.written)) continue;
+            if (!chunked(a)) continue;
             uintptr_t p = (uintptr_t)(*(void* const*)args[k]);
             int s = dtype_size(a.dtype);
             uintptr_t align = (uintptr_t)std::min(vec * s, 16);

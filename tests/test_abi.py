@@ -56,6 +56,24 @@ def test_classifier_read_write_sets():
     assert k.vec == 16                                 # 16 bytes of the narrowest array
 
 
+def test_fixed_element_reads_stay_on_the_vector_path():
+    # a device-resident scalar read as a[0] is the same element for every i:
+    # read directly, never moved in chunks, and it does not narrow VEC
+    k = hm.compile("x[i] += a[0] * p[i]", "float *x, const float *p, const double *a")
+    assert k.vectorizable and k.vec == 4
+    assert [(a.read, a.written) for a in k.args] == [(1, 1), (1, 0), (1, 0)]
+    src = k.source(0)
+    assert "hipmr_p_p[hipmr_u].v[hipmr_j]" in src and "a [ 0 ]" in src
+    assert "hipmr_p_a" not in src
+    r = hm.compile("s[1] * x[i]", "float: const float *x, const fp8_e4m3 *s")
+    assert r.vectorizable and r.vec == 4               # fp8 s is not chunked
+    # writing the array elsewhere keeps the one-element path
+    k = hm.compile("z[i] = z[0] + 1", "float *z")
+    assert not k.vectorizable
+    k = hm.compile("z[i] = x[n - 1]", "float *z, const float *x")
+    assert not k.vectorizable
+
+
 def test_generated_source_shape():
     k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y",
                    name="lin")

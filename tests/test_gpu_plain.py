@@ -366,3 +366,32 @@ def test_plain_at_scale_elementwise_sampled(dev, kernels, plain_data, name):
     assert torch.equal(z, z2)                           # bitwise repeatable
     del xd, yd, z, z2
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------- fixed-element reads
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_fixed_element_reads_vector_path(dev, offset):
+    """Device-resident scalars read as a[0] / a[1] stay on the 16-byte path
+    (the same element for every i, read directly)."""
+    n = 70001
+    rng = np.random.default_rng(95 + offset)
+    x = rng.uniform(-1, 1, n + 8).astype(np.float32)
+    p = rng.uniform(-1, 1, n + 8).astype(np.float32)
+    a = np.array([0.3125, -1.75], np.float64)
+    sig = "float *x, const float *p, const double *a"
+    stmt = "x[i] += (float)a[0] * p[i] - (float)a[1]"
+    k = hm.compile(stmt, sig, name="fixed_ew")
+    assert k.vectorizable
+    xd, pd, ad = dev_array(x), dev_array(p), dev_array(a)
+    xs, ps = x[offset:offset + n].copy(), p[offset:offset + n]
+    hm.elementwise(k, n, [xd[offset:offset + n], pd[offset:offset + n], ad])
+    torch.cuda.synchronize()
+    ref = oracle.elementwise(sig, stmt, n, [xs, ps, a])
+    assert_lanes(xd[offset:offset + n], ref["x"], "float32", what=f"fixed-element ew offset {offset}")
+    assert k.last_symbols()[0].split("_")[-2] == "ew"       # the vector kernel ran
+    # map-reduce with a fixed-element scale
+    r = hm.compile("s[1] * x[i]", "float: const float *x, const float *s", name="fixed_red")
+    s = np.array([9.0, 0.5], np.float32)
+    out = reduce_on_gpu(r, "a+b", "0", n, [xd[offset:offset + n], dev_array(s)])
+    assert_reduce(out, oracle.reduce("float: const float *x, const float *s", "s[1] * x[i]", "a+b", "0",
+                                     n, [x[offset:offset + n], s]), "fixed-element reduce")
