@@ -18,6 +18,8 @@ Generation with PyCUDA"):
 * ``scan``: the parallel prefix sums the paper lists among the further
   facilities -- every prefix of the map values folded from the neutral
   element, inclusive or exclusive (section "Further Facilities");
+* ``laplace5`` and ``cg``: the conjugate-gradient solver the paper lists
+  among the further facilities, on the five-point model problem;
 * decoders for the 16- and 8-bit float formats used by the precision
   extension, an exact sum and a norm.
 
@@ -32,8 +34,10 @@ from .ctype import parse_signature, round_fraction, f32_literal
 from .formats import decode_bf16, decode_e4m3fn, decode_f16
 from .reduce import ReduceResult, canonical_op, eval_neutral, exact_sum, norm2, reduce
 from .scan import ScanResult, scan
+from .cg import cg, laplace5
 
 __all__ = ["elementwise", "map_values", "map_chunks", "reduce", "ReduceResult", "scan", "ScanResult",
+           "cg", "laplace5",
            "canonical_op", "eval_neutral", "exact_sum", "norm2", "parse_signature",
            "round_fraction", "f32_literal", "decode_bf16", "decode_f16", "decode_e4m3fn",
            "Lanes", "OracleError", "CSyntaxError"]
