@@ -392,6 +392,7 @@ def test_fixed_element_reads_vector_path(dev, offset):
     # map-reduce with a fixed-element scale
     r = hm.compile("s[1] * x[i]", "float: const float *x, const float *s", name="fixed_red")
     s = np.array([9.0, 0.5], np.float32)
-    out = reduce_on_gpu(r, "a+b", "0", n, [xd[offset:offset + n], dev_array(s)])
+    x0d = dev_array(x)                                       # xd was updated above
+    out = reduce_on_gpu(r, "a+b", "0", n, [x0d[offset:offset + n], dev_array(s)])
     assert_reduce(out, oracle.reduce("float: const float *x, const float *s", "s[1] * x[i]", "a+b", "0",
                                      n, [x[offset:offset + n], s]), "fixed-element reduce")
