@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="precision,batched,served,scan",
+    p.add_argument("--extensions", default="precision,batched,served,scan,cg",
                    help="comma list of the extension measurements to run "
-                        "(precision, batched, served, scan)")
+                        "(precision, batched, served, scan, cg)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -175,6 +175,47 @@ def bench_scan(torch, hm, workloads, dev, stream, reps=10):
         del out
     del xd, kd
     torch.cuda.empty_cache()
+    return res
+
+
+def bench_cg(torch, hm, dev):
+    """Conjugate gradients on the five-point model problem: time per
+    iteration, eager (nine launches) and replayed from a HIP graph, on a
+    4096 x 4096 grid (bandwidth-bound) and a 256 x 256 grid (launch-bound);
+    52 algorithmic bytes per unknown and iteration."""
+    from paper_1304_5553_amd import cg as hcg
+    res = {"bytes_per_unknown": hcg.BYTES_PER_UNKNOWN}
+    for nx in (4096, 256):
+        n = nx * nx
+        rng = np.random.default_rng(8)
+        b = torch.from_numpy(rng.uniform(-1, 1, n).astype(np.float32)).to(dev)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            solver = hcg.PoissonCG(nx, nx, device=dev, stream=stream)
+            solver.solve(b, 2)                               # loads every kernel
+            graph = solver.capture(10)
+            row = {"n": n}
+            for mode in ("eager", "graph"):
+                solver.start(b)
+                stream.synchronize()
+                t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                t0.record(stream)
+                for _ in range(5):
+                    if mode == "graph":
+                        graph.launch(stream)
+                    else:
+                        for _ in range(10):
+                            solver.step()
+                t1.record(stream)
+                stream.synchronize()
+                ms = t0.elapsed_time(t1) / 50
+                row[mode] = {"ms_per_iter": round(ms, 5),
+                             "GB/s": round(hcg.BYTES_PER_UNKNOWN * n / ms / 1e6, 1)}
+            row["graph_speedup"] = round(row["eager"]["ms_per_iter"] / row["graph"]["ms_per_iter"], 2)
+            row["rr_after_50"] = float(solver.s[0].item())
+        res[f"{nx}x{nx}"] = row
+        del solver, graph, b
+        torch.cuda.empty_cache()
     return res
 
 
@@ -463,6 +504,9 @@ def main():
     if "scan" in ext:
         line["scan"] = bench_scan(torch, hm, workloads, dev, stream)
         print("scan done", file=sys.stderr, flush=True)
+    if "cg" in ext:
+        line["cg"] = bench_cg(torch, hm, dev)
+        print("cg done", file=sys.stderr, flush=True)
     if "served" in ext:
         rates = tuple(int(r) for r in args.serving_rates.split(",") if r.strip()) or None
         line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration,
