@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="precision,batched,served,scan,cg",
+    p.add_argument("--extensions", default="precision,batched,served,scan,cg,lazy",
                    help="comma list of the extension measurements to run "
-                        "(precision, batched, served, scan, cg)")
+                        "(precision, batched, served, scan, cg, lazy)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -217,6 +217,39 @@ def bench_cg(torch, hm, dev):
         del solver, graph, b
         torch.cuda.empty_cache()
     return res
+
+
+def bench_lazy(torch, dev, stream, reps=10):
+    """The temporaries problem: z = 2.5 x y + sqrt(x x + y y) - 0.5 w over
+    n = 2^26 float32, as one fused generated kernel (16 B/element) and as one
+    kernel per operator (each writing a temporary)."""
+    from paper_1304_5553_amd import lazy as lz
+    n = 1 << 26
+    rng = np.random.default_rng(9)
+    x, y, w = (torch.from_numpy(rng.uniform(-1, 1, n).astype(np.float32)).to(dev) for _ in range(3))
+    X, Y, W = lz.lazy(x), lz.lazy(y), lz.lazy(w)
+    expr = 2.5 * X * Y + lz.sqrt(X * X + Y * Y) - 0.5 * W
+    out = torch.empty(n, device=dev)
+    fused_ms = _time_ms(torch, lambda: expr.eval(out=out), reps, stream)
+    unfused_ms = _time_ms(torch, lambda: expr.eval(out=out, fused=False), reps, stream)
+    # unfused traffic: every operator reads its array operands and writes a temporary
+    def count(node):
+        if node.op in ("leaf", "const"):
+            return 0, 0
+        k, b = 0, 0
+        for a in node.args:
+            kk, bb = count(a)
+            k, b = k + kk, b + bb
+        return k + 1, b + 4 * (sum(1 for a in node.args if a.op != "const") + 1)
+    kernels, per = count(expr)
+    del x, y, w, out
+    torch.cuda.empty_cache()
+    return {"n": n, "expression": "2.5*x*y + sqrt(x*x + y*y) - 0.5*w",
+            "fused": {"ms": round(fused_ms, 4), "kernels": 1, "bytes_per_element": 16,
+                      "GB/s": round(16 * n / fused_ms / 1e6, 1)},
+            "unfused": {"ms": round(unfused_ms, 4), "kernels": kernels, "bytes_per_element": per,
+                        "GB/s": round(per * n / unfused_ms / 1e6, 1)},
+            "speedup": round(unfused_ms / fused_ms, 2)}
 
 
 def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
@@ -504,6 +537,9 @@ def main():
     if "scan" in ext:
         line["scan"] = bench_scan(torch, hm, workloads, dev, stream)
         print("scan done", file=sys.stderr, flush=True)
+    if "lazy" in ext:
+        line["lazy"] = bench_lazy(torch, dev, stream)
+        print("lazy done", file=sys.stderr, flush=True)
     if "cg" in ext:
         line["cg"] = bench_cg(torch, hm, dev)
         print("cg done", file=sys.stderr, flush=True)

@@ -1,0 +1,61 @@
+"""GPU parity of the lazy expression front end: an operator tree fused into
+one generated kernel (and, for comparison, one kernel per operator) against
+the oracle's evaluation of the rendered statement; fused reductions against
+the oracle's map-reduce."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_lanes, assert_reduce, need_gpu, torch
+import oracle
+from paper_1304_5553_amd import lazy as lz
+from test_lazy import EXPRS, leaves
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def host_arrays(ts):
+    return [t.view(torch.int16).numpy().view(np.uint16) if t.dtype == torch.bfloat16 else t.numpy()
+            for t in ts]
+
+
+@pytest.mark.parametrize("name", list(EXPRS))
+@pytest.mark.parametrize("dts", [("float32",) * 3, ("bfloat16", "float32", "int32")])
+@pytest.mark.parametrize("fused", [True, False])
+def test_lazy_elementwise(dev, name, dts, fused):
+    n = 100003
+    ts = leaves(n, 11, dts)
+    ds = [t.to(dev) for t in ts]
+    node = EXPRS[name](*(lz.lazy(t) for t in ds))
+    got = node.eval(fused=fused)
+    torch.cuda.synchronize()
+    dtypes, stmt, lv = lz.elementwise_source(node)
+    order = [next(k for k, d in enumerate(ds) if d is t) for t in lv]
+    ref = oracle.elementwise(dtypes, stmt, n, [np.zeros(n, np.float32)] + host_arrays([ts[k] for k in order]))
+    assert_lanes(got, ref["out"], "float32", what=f"{name} {dts} fused={fused}")
+
+
+@pytest.mark.parametrize("red", ["sum", "max", "min", "dot"])
+def test_lazy_reductions(dev, red):
+    n = 200001
+    ts = leaves(n, 12)
+    ds = [t.to(dev) for t in ts]
+    x, y, w = (lz.lazy(t) for t in ds)
+    node = x * y - 0.5 * w if red != "dot" else None
+    if red == "dot":
+        out = lz.dot(x, lz.sqrt(y))
+        node, comb, neu = x * lz.sqrt(y), "a+b", "0"
+    else:
+        out = getattr(node, red)()
+        comb, neu = {"sum": ("a+b", "0"), "max": ("max(a,b)", "-INFINITY"),
+                     "min": ("min(a,b)", "INFINITY")}[red]
+    torch.cuda.synchronize()
+    dtypes, expr, lv = lz.reduce_source(node)
+    order = [next(k for k, d in enumerate(ds) if d is t) for t in lv]
+    r = oracle.reduce(dtypes, expr, comb, neu, n, host_arrays([ts[k] for k in order]))
+    assert_reduce(out, r, red)
