@@ -8,7 +8,9 @@ dtype (section "Map-Reduce").  This module parses that list on its own
 the interpreter evaluates.
 
 Value types: ``int`` (32-bit signed), ``unsigned`` (32-bit), ``long``
-(64-bit signed), ``float`` and ``double``.  Integer values are held as
+(64-bit signed), ``float``, ``double`` and ``cfloat`` (complex with float
+components, stored as ``complex64``; held as complex128 ideal values with a
+bound on the magnitude of the error).  Integer values are held as
 exact int64; floating values are held in float64 as the *ideal* value of
 the expression, with a separate absolute error bound for what a float32
 (or float64) evaluation may produce.
@@ -25,6 +27,7 @@ from .lexer import CSyntaxError, tokenize
 from .parser import TYPE_WORDS
 
 INT, UINT, LONG, FLOAT, DOUBLE = "int", "unsigned", "long", "float", "double"
+CFLOAT = "cfloat"            # complex with float components (section "Complex Numbers on the GPU")
 INT_TYPES = (INT, UINT, LONG)
 FLOAT_TYPES = (FLOAT, DOUBLE)
 
@@ -35,24 +38,29 @@ STORAGE_VT = {
     "int8": INT, "uint8": INT, "int16": INT, "uint16": INT, "int32": INT,
     "uint32": UINT, "int64": LONG, "bool": INT,
     "bfloat16": FLOAT, "float16": FLOAT, "fp8_e4m3": FLOAT,
+    "complex64": CFLOAT,
 }
 STORAGE_BYTES = {"float32": 4, "float64": 8, "int8": 1, "uint8": 1, "int16": 2,
                  "uint16": 2, "int32": 4, "uint32": 4, "int64": 8, "bool": 1,
-                 "bfloat16": 2, "float16": 2, "fp8_e4m3": 1}
+                 "bfloat16": 2, "float16": 2, "fp8_e4m3": 1, "complex64": 8}
 NUMPY_STORAGE = {"float32": np.float32, "float64": np.float64, "int8": np.int8,
                  "uint8": np.uint8, "int16": np.int16, "uint16": np.uint16,
                  "int32": np.int32, "uint32": np.uint32, "int64": np.int64,
-                 "bfloat16": np.uint16, "float16": np.uint16, "fp8_e4m3": np.uint8}
+                 "bfloat16": np.uint16, "float16": np.uint16, "fp8_e4m3": np.uint8,
+                 "complex64": np.complex64}
 
-UNIT = {FLOAT: 2.0 ** -24, DOUBLE: 2.0 ** -53}
+UNIT = {FLOAT: 2.0 ** -24, DOUBLE: 2.0 ** -53, CFLOAT: 2.0 ** -24}
 # absolute slack per rounding: covers gradual underflow and flush-to-zero
-TINY = {FLOAT: 2.0 ** -126, DOUBLE: 2.0 ** -1022}
+TINY = {FLOAT: 2.0 ** -126, DOUBLE: 2.0 ** -1022, CFLOAT: 2.0 ** -126}
 INT_RANGE = {INT: (-2 ** 31, 2 ** 31 - 1), UINT: (0, 2 ** 32 - 1),
              LONG: (-2 ** 63, 2 ** 63 - 1)}
 
 
 def common_type(a: str, b: str) -> str:
-    """C usual arithmetic conversions over the value types (LP64)."""
+    """C usual arithmetic conversions over the value types (LP64); a complex
+    operand makes the operation complex with float components."""
+    if CFLOAT in (a, b):
+        return CFLOAT
     if DOUBLE in (a, b):
         return DOUBLE
     if FLOAT in (a, b):

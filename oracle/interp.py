@@ -39,7 +39,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import formats
-from .ctype import (DOUBLE, FLOAT, FLOAT_TYPES, INT, INT_RANGE, INT_TYPES, LONG,
+from .ctype import (CFLOAT, DOUBLE, FLOAT, FLOAT_TYPES, INT, INT_RANGE, INT_TYPES, LONG,
                     STORAGE_VT, TINY, UINT, UNIT, common_type, f32_literal)
 from .lexer import CSyntaxError
 from .parser import (Assign, Binary, Block, Call, Cast, Comma, Cond, Decl, ExprStmt,
@@ -113,7 +113,7 @@ class Interp:
             v = _bcast(np.asarray(v, dtype=np.int64), L)
             e = np.zeros(L)
         else:
-            v = _bcast(np.asarray(v, dtype=np.float64), L)
+            v = _bcast(np.asarray(v, dtype=np.complex128 if t == CFLOAT else np.float64), L)
             e = self._zeros_e() if e is None else _bcast(np.asarray(e, dtype=np.float64), L)
         u = np.zeros(L, dtype=bool) if u is None else _bcast(np.asarray(u, dtype=bool), L)
         return Val(t, v, e, u)
@@ -128,6 +128,8 @@ class Interp:
             return self._mk(vt, self.decode(storage, np.asarray([int(value)]))[0])
         if storage == "float32":
             value = float(np.float32(value))
+        if storage == "complex64":
+            return self._mk(vt, complex(np.complex64(value)))
         return self._mk(vt, float(value))
 
     def decode(self, storage, raw):
@@ -139,12 +141,19 @@ class Interp:
             return formats.decode_e4m3fn(raw)
         if STORAGE_VT[storage] in INT_TYPES:
             return np.asarray(raw).astype(np.int64)
+        if storage == "complex64":
+            return np.asarray(raw).astype(np.complex128)
         return np.asarray(raw).astype(np.float64)
 
     # -- type conversion (C rules)
     def convert(self, x: Val, t: str, active) -> Val:
         if x.t == t:
             return x
+        if x.t == CFLOAT:
+            raise CSyntaxError("a complex value becomes real only through real(), imag() or abs()")
+        if t == CFLOAT:            # real -> complex: the float conversion, imaginary part 0
+            y = self.convert(x, FLOAT, active)
+            return Val(CFLOAT, y.v.astype(np.complex128), y.e, y.u)
         if t in INT_TYPES:
             if x.t in INT_TYPES:
                 if t == LONG:
@@ -206,6 +215,8 @@ class Interp:
 
     # -- truth values
     def truth(self, x: Val):
+        if x.t == CFLOAT:
+            raise CSyntaxError("a complex value has no truth value")
         return x.v != 0
 
     def truth_unsure(self, x: Val):
@@ -421,7 +432,7 @@ class Interp:
         if node.op == "+":
             return x
         if node.op == "-":
-            if x.t in FLOAT_TYPES:
+            if x.t in FLOAT_TYPES or x.t == CFLOAT:
                 return Val(x.t, -x.v, x.e, x.u)
             return self._int_result(x.t, -x.v, x.u, active)
         if node.op == "~":
@@ -451,6 +462,10 @@ class Interp:
         t = common_type(a.t, b.t)
         a, b = self.convert(a, t, active), self.convert(b, t, active)
         u = a.u | b.u
+        if t == CFLOAT:
+            if op not in ("+", "-", "*"):
+                raise CSyntaxError(f"operator {op} is not supported on complex values")
+            return self._complex_arith(op, a, b, u)
         if op in ("==", "!=", "<", ">", "<=", ">="):
             return self._compare(op, a, b, u)
         if t in FLOAT_TYPES:
@@ -493,6 +508,26 @@ class Interp:
             e = np.where(np.isnan(e) & np.isfinite(v), np.inf, e)
             u = u | (~np.isfinite(e) & np.isfinite(v))
         return Val(t, v, e, u)
+
+    def _complex_arith(self, op, a, b, u):
+        """Complex +, -, * with float components.  Each component of a sum
+        rounds once (|error| <= u |v|); a product's components each take
+        two products and a sum (with or without fused multiply-add), so its
+        error is at most 2 sqrt(2) u |a| |b| in magnitude."""
+        ut = UNIT[CFLOAT]
+        with np.errstate(all="ignore"):
+            if op in ("+", "-"):
+                v = a.v + b.v if op == "+" else a.v - b.v
+                prop = a.e + b.e
+                e = prop + ut * (np.abs(v) + prop)
+            else:
+                v = a.v * b.v
+                prop = np.abs(a.v) * b.e + np.abs(b.v) * a.e + a.e * b.e
+                e = prop + 2 * math.sqrt(2) * ut * (np.abs(a.v) + a.e) * (np.abs(b.v) + b.e)
+            e = e + 2 * TINY[CFLOAT] + EPS64 * np.abs(v)
+            e = np.where(np.isnan(e) & np.isfinite(v), np.inf, e)
+            u = u | (~np.isfinite(e) & np.isfinite(v))
+        return Val(CFLOAT, v, e, u)
 
     def _int_arith(self, op, a, b, t, u, active):
         x, y = a.v, b.v
@@ -567,11 +602,33 @@ class Interp:
     GENERIC = {"sqrt", "fabs", "exp", "log", "sin", "cos", "floor", "ceil", "trunc",
                "fmax", "fmin", "max", "min", "abs"}
 
+    def _complex_call(self, f, args, active):
+        """conj, real, imag and abs of a complex value (abs as the square root
+        of the sum of the squared components: three roundings and the
+        square root's)."""
+        if len(args) != 1:
+            raise CSyntaxError(f"{f} takes 1 argument")
+        z = self.convert(args[0], CFLOAT, active)
+        if f == "conj":
+            return Val(CFLOAT, np.conj(z.v), z.e, z.u)
+        if f in ("real", "imag"):
+            return Val(FLOAT, z.v.real if f == "real" else z.v.imag, z.e, z.u)
+        with np.errstate(all="ignore"):
+            v = np.abs(z.v)
+            e = z.e + 4 * UNIT[FLOAT] * (v + z.e) + TINY[FLOAT] + EPS64 * v
+        return Val(FLOAT, v, e, z.u)
+
     def _e_Call(self, node, active):
         f = node.func
+        if f in ("conj", "real", "imag"):
+            return self._complex_call(f, [self.eval(x, active) for x in node.args], active)
         if f not in self.F_SUFFIX and f not in self.GENERIC:
             raise CSyntaxError(f"unsupported function {f!r}")
         args = [self.eval(x, active) for x in node.args]
+        if f == "abs" and len(args) == 1 and args[0].t == CFLOAT:
+            return self._complex_call(f, args, active)
+        if any(x.t == CFLOAT for x in args):
+            raise CSyntaxError(f"{f} of a complex value is not supported")
         base = f[:-1] if f in self.F_SUFFIX else f
         nargs = 2 if base in ("fmax", "fmin", "max", "min") else 1
         if len(args) != nargs:

@@ -34,6 +34,7 @@ TYPE_WORDS = {
     ("half",): "float16", ("__half",): "float16", ("_Float16",): "float16",
     ("float16",): "float16",
     ("fp8_e4m3",): "fp8_e4m3",
+    ("complex64",): "complex64", ("cfloat",): "complex64",
 }
 _TYPE_FIRST = {w[0] for w in TYPE_WORDS}
 

@@ -16,6 +16,7 @@ commutative; the oracle computes the order-free value wherever one exists:
 * floating sums: the exact real sum of the map values, correctly rounded to
   float64 (``math.fsum``, Shewchuk's algorithm), together with sum |m_i| and
   the sum of the per-value error bounds, which the tolerance is built from;
+  complex sums the same, for the real and imaginary parts separately;
 * max / min of floating values: IEEE 754-2019 ``maximum`` / ``minimum``
   (a NaN anywhere gives NaN, -0 orders below +0); of integers: exact;
 * any other reduce expression: a left-to-right fold evaluated with C
@@ -35,7 +36,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .api import map_chunks
-from .ctype import FLOAT_TYPES, INT, INT_RANGE, LONG, STORAGE_VT, UINT, parse_signature
+from .ctype import CFLOAT, FLOAT_TYPES, INT, INT_RANGE, LONG, STORAGE_VT, UINT, parse_signature
 from .interp import Interp, OracleError
 from .parser import parse_expression
 
@@ -92,6 +93,20 @@ def reduce(dtypes, map_expr, combine, neutral, n, args) -> ReduceResult:
     neutral_val = eval_neutral(sig.result, neutral)
     chunks = map_chunks(dtypes, map_expr, n, args)
     unsure = 0
+
+    if rt == CFLOAT and op != "generic":
+        if op != "sum":
+            raise OracleError("complex values have no order: only sums reduce them")
+        vals, abs_sum, err_sum = [], 0.0, 0.0
+        for _, val in chunks:
+            unsure += int(np.count_nonzero(val.u))
+            vals.append(val.v)
+            abs_sum += float(np.sum(np.abs(val.v)))
+            err_sum += float(np.sum(val.e))
+        allv = np.concatenate([np.asarray([complex(neutral_val.v[0])])] + vals)
+        value = complex(math.fsum(allv.real.tolist()), math.fsum(allv.imag.tolist()))
+        return ReduceResult(value, op, rt, n, abs_sum * (1 + 1e-12), err_sum * (1 + 1e-12),
+                            unsure, False)
 
     if op == "sum" and rt not in FLOAT_TYPES:
         total = int(neutral_val.v[0])
@@ -155,8 +170,8 @@ def reduce(dtypes, map_expr, combine, neutral, n, args) -> ReduceResult:
             it.locals["b"] = (storage, it._mk(rt, x))
             res = it.to_storage(it.eval(expr, one), storage, one)
             acc = res.v[0]
-    value = float(acc) if rt in FLOAT_TYPES else int(acc)
-    return ReduceResult(value, op, rt, n, 0.0, 0.0, unsure, rt not in FLOAT_TYPES)
+    value = complex(acc) if rt == CFLOAT else float(acc) if rt in FLOAT_TYPES else int(acc)
+    return ReduceResult(value, op, rt, n, 0.0, 0.0, unsure, rt not in FLOAT_TYPES and rt != CFLOAT)
 
 
 def exact_sum(values) -> float:
