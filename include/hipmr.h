@@ -69,11 +69,16 @@ typedef int32_t hipmr_status;
  *   float | double | int8_t, char, signed char | uint8_t, unsigned char |
  *   int16_t, short | uint16_t, unsigned short | int32_t, int, signed |
  *   uint32_t, unsigned, unsigned int | int64_t, long, long long |
- *   bfloat16, __hip_bfloat16 | half, __half, float16 | fp8_e4m3
+ *   bfloat16, __hip_bfloat16 | half, __half, float16 | fp8_e4m3 |
+ *   complex64, cfloat
  * bfloat16, half and fp8_e4m3 (OCP E4M3, "fn": no infinities, max 448) are
  * storage types: a read converts exactly to float, and all arithmetic on
  * them happens in float; a store rounds to nearest even (fp8 saturates to
- * +-448). */
+ * +-448).  complex64 is a complex value with float components (real,
+ * imaginary; 8 bytes), the complex support of section "Complex Numbers on
+ * the GPU": +, - and * with complex or real operands, unary -, conj(z),
+ * real(z), imag(z) and abs(z); no division, no ordering; as a reduce
+ * result only with the sum combine. */
 #define HIPMR_F32   1
 #define HIPMR_F64   2
 #define HIPMR_I8    3
@@ -86,6 +91,7 @@ typedef int32_t hipmr_status;
 #define HIPMR_BF16 10
 #define HIPMR_F16  11
 #define HIPMR_FP8  12
+#define HIPMR_C64  13
 
 typedef struct hipmr_kernel *hipmr_handle;
 

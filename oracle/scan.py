@@ -17,10 +17,10 @@ computes the order-free value of every prefix:
 * integer sums: exact prefix sums (Python integers), then the result type's
   rule (int64 / int32 must not overflow; unsigned wraps modulo 2**32);
 * floating sums: every prefix's exact real sum, correctly rounded to
-  float64.  The map values are moved to a common binary fixed point (a
-  Python integer times 2**-S, exact for every float64), summed there
-  exactly, and each prefix is rounded once by Python's correctly rounded
-  integer division.  The prefix sums of |m| and of the map values' error
+  float64 (for complex values, the real and imaginary parts separately).
+  The map values are moved to a common binary fixed point (a Python integer
+  times 2**-S, exact for every float64), summed there exactly, and each
+  prefix is rounded once by Python's correctly rounded integer division.  The prefix sums of |m| and of the map values' error
   bounds are returned for the tolerance;
 * max / min of floating values: IEEE 754-2019 ``maximum`` / ``minimum`` of
   every prefix (a NaN propagates to every later prefix; -0 orders below
@@ -36,7 +36,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .api import map_chunks
-from .ctype import FLOAT_TYPES, INT_RANGE, STORAGE_VT, UINT, parse_signature
+from .ctype import CFLOAT, FLOAT_TYPES, INT_RANGE, STORAGE_VT, UINT, parse_signature
 from .interp import Interp, OracleError
 from .parser import parse_expression
 from .reduce import GENERIC_FOLD_LIMIT, canonical_op, eval_neutral
@@ -101,7 +101,16 @@ def scan(dtypes, map_expr, combine, neutral, n, args, exclusive=False) -> ScanRe
     # prefix values over [neutral, m0, ..., m(n-1)]: entry k holds k map terms
     abs_p = np.zeros(n + 1)
     err_p = np.zeros(n + 1)
-    if op == "sum" and rt not in FLOAT_TYPES:
+    if rt == CFLOAT and op != "generic":
+        if op != "sum":
+            raise OracleError("complex values have no order: only sums scan them")
+        neu = complex(neutral_val.v[0])
+        prefix = (_exact_float_prefix(neu.real, m.real) + 1j * _exact_float_prefix(neu.imag, m.imag))
+        pad = 1.0 + (n + 1) * 2.0 ** -52
+        abs_p[1:] = np.cumsum(np.abs(m)) * pad
+        err_p[1:] = np.cumsum(e) * pad
+        exact = False
+    elif op == "sum" and rt not in FLOAT_TYPES:
         acc = int(neutral_val.v[0])
         pref = [acc]
         for x in m.tolist():

@@ -73,6 +73,9 @@ std::string spec_key(const KernelSpec& s) {
 }
 
 hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_ptr<CodeObject>* out) {
+    if (h->prog.sig.result == DT_C64 && !spec.combine.empty() &&
+        canonical_combine(spec.combine) != Combine::Sum && canonical_combine(spec.combine) != Combine::Generic)
+        return fail(HIPMR_E_UNSUPPORTED, "complex values have no order: reduce them with a sum");
     std::string k = spec_key(spec);
     {
         std::lock_guard<std::mutex> lk(h->mu);
@@ -170,9 +173,9 @@ hipmr_status make_handle(const char* expr, const char* dtypes, const char* name,
     if (st != HIPMR_OK) return st;
     if (h->prog.sig.is_reduce) {
         DType r = h->prog.sig.result;
-        if (!(r == DT_F32 || r == DT_F64 || r == DT_I32 || r == DT_U32 || r == DT_I64))
+        if (!(r == DT_F32 || r == DT_F64 || r == DT_I32 || r == DT_U32 || r == DT_I64 || r == DT_C64))
             return fail(HIPMR_E_UNSUPPORTED, "reduce result type must be float, double, int, "
-                                             "unsigned or a 64-bit integer");
+                                             "unsigned, a 64-bit integer or complex64");
     }
     h->default_vec = default_vec_for(h->prog.sig);
     if (!h->prog.sig.is_reduce) {
@@ -639,6 +642,9 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         {"x[i]", "float: const fp8_e4m3 *x", "a+b", "0"},
         {"x[i]", "float: const bfloat16 *x", "a+b", "0"},
         {"x[i] * y[i]", "float: const half *x, const half *y", "a+b", "0"},
+        {"z[i] = conj(x[i]) * y[i] + a * x[i]", "complex64 *z, const complex64 *x, const complex64 *y, complex64 a",
+         nullptr, nullptr},
+        {"conj(x[i]) * y[i]", "complex64: const complex64 *x, const complex64 *y", "a+b", "0"},
     };
     int32_t built = 0;
     for (const Case& c : cases) {

@@ -121,6 +121,46 @@ struct hipmr_fp8 {
   __device__ __forceinline__ hipmr_fp8& operator/=(float f) { return *this = (float)*this / f; }
 };
 
+// Complex values with float components (real, imaginary).
+struct hipmr_c64 {
+  float re, im;
+  hipmr_c64() = default;
+  __device__ __forceinline__ constexpr hipmr_c64(float r, float i) : re(r), im(i) {}
+  __device__ __forceinline__ constexpr hipmr_c64(float r) : re(r), im(0.0f) {}
+  __device__ __forceinline__ constexpr hipmr_c64(double r) : re((float)r), im(0.0f) {}
+  __device__ __forceinline__ constexpr hipmr_c64(int r) : re((float)r), im(0.0f) {}
+  __device__ __forceinline__ constexpr hipmr_c64(unsigned int r) : re((float)r), im(0.0f) {}
+  __device__ __forceinline__ constexpr hipmr_c64(long long r) : re((float)r), im(0.0f) {}
+  __device__ __forceinline__ hipmr_c64& operator+=(hipmr_c64 b) { re += b.re; im += b.im; return *this; }
+  __device__ __forceinline__ hipmr_c64& operator-=(hipmr_c64 b) { re -= b.re; im -= b.im; return *this; }
+  __device__ __forceinline__ hipmr_c64& operator*=(hipmr_c64 b) {
+    const float r = re * b.re - im * b.im;
+    im = re * b.im + im * b.re;
+    re = r;
+    return *this;
+  }
+};
+__device__ __forceinline__ hipmr_c64 operator+(hipmr_c64 a, hipmr_c64 b) { return hipmr_c64(a.re + b.re, a.im + b.im); }
+__device__ __forceinline__ hipmr_c64 operator-(hipmr_c64 a, hipmr_c64 b) { return hipmr_c64(a.re - b.re, a.im - b.im); }
+__device__ __forceinline__ hipmr_c64 operator-(hipmr_c64 a) { return hipmr_c64(-a.re, -a.im); }
+__device__ __forceinline__ hipmr_c64 operator+(hipmr_c64 a) { return a; }
+__device__ __forceinline__ hipmr_c64 operator*(hipmr_c64 a, hipmr_c64 b) {
+  return hipmr_c64(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+__device__ __forceinline__ hipmr_c64 conj(hipmr_c64 z) { return hipmr_c64(z.re, -z.im); }
+__device__ __forceinline__ float real(hipmr_c64 z) { return z.re; }
+__device__ __forceinline__ float imag(hipmr_c64 z) { return z.im; }
+__device__ __forceinline__ float abs(hipmr_c64 z) { return __builtin_sqrtf(z.re * z.re + z.im * z.im); }
+__device__ __forceinline__ hipmr_c64 __shfl_xor(hipmr_c64 v, int m, int w) {
+  return hipmr_c64(__shfl_xor(v.re, m, w), __shfl_xor(v.im, m, w));
+}
+__device__ __forceinline__ hipmr_c64 __shfl_up(hipmr_c64 v, unsigned int d, int w) {
+  return hipmr_c64(__shfl_up(v.re, d, w), __shfl_up(v.im, d, w));
+}
+__device__ __forceinline__ hipmr_c64 __shfl(hipmr_c64 v, int l, int w) {
+  return hipmr_c64(__shfl(v.re, l, w), __shfl(v.im, l, w));
+}
+
 // A vector chunk of N elements held in registers.
 template <typename T, int N> struct hipmr_pack { T v[N]; };
 

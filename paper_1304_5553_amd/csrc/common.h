@@ -26,6 +26,7 @@ enum DType : int32_t {
     DT_F32 = HIPMR_F32, DT_F64 = HIPMR_F64, DT_I8 = HIPMR_I8, DT_U8 = HIPMR_U8,
     DT_I16 = HIPMR_I16, DT_U16 = HIPMR_U16, DT_I32 = HIPMR_I32, DT_U32 = HIPMR_U32,
     DT_I64 = HIPMR_I64, DT_BF16 = HIPMR_BF16, DT_F16 = HIPMR_F16, DT_FP8 = HIPMR_FP8,
+    DT_C64 = HIPMR_C64,
 };
 
 int dtype_size(DType t);

@@ -34,7 +34,7 @@ const char* last_error() { return g_last_error.c_str(); }
 int dtype_size(DType t) {
     switch (t) {
         case DT_F32: case DT_I32: case DT_U32: return 4;
-        case DT_F64: case DT_I64: return 8;
+        case DT_F64: case DT_I64: case DT_C64: return 8;
         case DT_I16: case DT_U16: case DT_BF16: case DT_F16: return 2;
         case DT_I8: case DT_U8: case DT_FP8: return 1;
         default: return 0;
@@ -55,6 +55,7 @@ const char* dtype_device_name(DType t) {
         case DT_BF16: return "hipmr_bf16";
         case DT_F16: return "hipmr_f16";
         case DT_FP8: return "hipmr_fp8";
+        case DT_C64: return "hipmr_c64";
         default: return "void";
     }
 }
@@ -80,6 +81,7 @@ const std::map<std::string, DType>& type_words() {
         {"bfloat16", DT_BF16}, {"__hip_bfloat16", DT_BF16},
         {"half", DT_F16}, {"__half", DT_F16}, {"float16", DT_F16}, {"_Float16", DT_F16},
         {"fp8_e4m3", DT_FP8},
+        {"complex64", DT_C64}, {"cfloat", DT_C64},
     };
     return m;
 }

@@ -25,10 +25,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhipmr.so")
 
 OK = 0
-F32, F64, I8, U8, I16, U16, I32, U32, I64, BF16, F16, FP8 = range(1, 13)
+F32, F64, I8, U8, I16, U16, I32, U32, I64, BF16, F16, FP8, C64 = range(1, 14)
 DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "int16_t",
                U16: "uint16_t", I32: "int", U32: "unsigned", I64: "int64_t",
-               BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3"}
+               BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3", C64: "complex64"}
 
 CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
 CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES, CFG_SEG_GLOBAL = 8, 16, 32
@@ -200,7 +200,8 @@ def _config(cfg):
 
 _CTYPE = {F32: ctypes.c_float, F64: ctypes.c_double, I8: ctypes.c_int8, U8: ctypes.c_uint8,
           I16: ctypes.c_int16, U16: ctypes.c_uint16, I32: ctypes.c_int32, U32: ctypes.c_uint32,
-          I64: ctypes.c_int64, BF16: ctypes.c_uint16, F16: ctypes.c_uint16, FP8: ctypes.c_uint8}
+          I64: ctypes.c_int64, BF16: ctypes.c_uint16, F16: ctypes.c_uint16, FP8: ctypes.c_uint8,
+          C64: ctypes.c_float * 2}
 
 
 def torch_dtype(code):
@@ -208,7 +209,7 @@ def torch_dtype(code):
     return {F32: torch.float32, F64: torch.float64, I8: torch.int8, U8: torch.uint8,
             I16: torch.int16, U16: torch.uint16, I32: torch.int32, U32: torch.uint32,
             I64: torch.int64, BF16: torch.bfloat16, F16: torch.float16,
-            FP8: torch.float8_e4m3fn}[code]
+            FP8: torch.float8_e4m3fn, C64: torch.complex64}[code]
 
 
 def _lowp_bits(code, value):
@@ -277,6 +278,9 @@ class Kernel:
                 c = ctypes.c_void_p(p)
             elif decl.dtype in (BF16, F16, FP8):
                 c = _CTYPE[decl.dtype](_lowp_bits(decl.dtype, val))
+            elif decl.dtype == C64:
+                z = complex(val)
+                c = _CTYPE[C64](z.real, z.imag)
             else:
                 c = _CTYPE[decl.dtype](val)
             keep.append(c)

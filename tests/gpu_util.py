@@ -49,6 +49,8 @@ def decoded(t, storage):
         return oracle.decode_f16(bits)
     if storage == "fp8_e4m3":
         return oracle.decode_e4m3fn(bits)
+    if bits.dtype.kind == "c":
+        return bits.astype(np.complex128)
     return bits.astype(np.float64) if bits.dtype.kind == "f" else bits.astype(np.int64)
 
 

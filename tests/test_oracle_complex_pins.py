@@ -85,3 +85,13 @@ def test_conversions_and_unsupported_operations():
         oracle.reduce("complex64: const complex64 *x", "x[i]", "max(a,b)", "0", 1, [x])
     r = oracle.elementwise(SIG, "z[i] = 3 + x[i]", 1, [np.zeros(1, np.complex64), x, x])
     assert r["z"].v.tolist() == [4 + 1j]
+
+
+def test_complex_prefix_scan_is_fsum_per_part():
+    rng = np.random.default_rng(4)
+    n = 300
+    x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    r = oracle.scan("complex64: const complex64 *x", "x[i]", "a+b", "0", n, [x])
+    re, im = x.real.astype(np.float64).tolist(), x.imag.astype(np.float64).tolist()
+    for k in range(0, n, 13):
+        assert r.values[k] == complex(math.fsum(re[:k + 1]), math.fsum(im[:k + 1]))
