@@ -241,7 +241,7 @@ hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void *const *args, double po
 
 /* ------------------------------------------------------------------ prefix scan */
 
-/* Bytes of device workspace hipmr_scan needs (two tables of at most 16384
+/* Bytes of device workspace hipmr_scan needs (two tables of at most 65536
  * wave totals of the result type); 0 for an elementwise or invalid handle. */
 size_t hipmr_scan_workspace_bytes(hipmr_handle h, int64_t n);
 

@@ -1067,58 +1067,58 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
-// Pass 2: exclusive scan of the wave totals by one block of 1024 threads;
-// thread t takes a contiguous run of at most 16 of them (all loaded before
-// any is combined).
+// Pass 2, in two launches over the wave totals (coalesced, one per thread):
+// every block of 1024 scans its 1024 totals (exclusive, within the block)
+// and writes the block total; then one block scans the block totals.
 const char* kScanMid = R"HIP(
-extern "C" __global__ void __launch_bounds__(1024)
-@@KNAME@@(const hipmr_acc* __restrict__ hipmr_partial, long long hipmr_waves,
-          hipmr_acc* __restrict__ hipmr_prefix)
-{
-  constexpr int B = 1024, W = B / 64, R = 16;
+template <int B>
+__device__ __forceinline__ hipmr_acc hipmr_block_exclusive(hipmr_acc v, hipmr_acc neutral, hipmr_acc* total) {
+  constexpr int W = B / 64;
   __shared__ hipmr_acc hipmr_wt[W];
-  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long long per = (hipmr_waves + B - 1) / B;          // <= R (at most 16384 waves)
-  const long long t0 = (long long)threadIdx.x * per;
-  hipmr_acc v[R];
-#pragma unroll
-  for (int k = 0; k < R; ++k)
-    v[k] = k < per && t0 + k < hipmr_waves ? hipmr_partial[t0 + k] : hipmr_neutral;
-  hipmr_acc tot = hipmr_neutral;
-#pragma unroll
-  for (int k = 0; k < R; ++k)
-    if (k < per && t0 + k < hipmr_waves) tot = hipmr_combine(tot, v[k]);
-  const hipmr_acc x = hipmr_wave_scan(tot, lane, hipmr_neutral);
+  const hipmr_acc x = hipmr_wave_scan(v, lane, neutral);
   if (lane == 63) hipmr_wt[w] = x;
   __syncthreads();
   if (w == 0) {
-    hipmr_acc v = lane < W ? hipmr_wt[lane] : hipmr_neutral;
-    v = hipmr_wave_scan(v, lane, hipmr_neutral);
-    if (lane < W) hipmr_wt[lane] = v;
+    hipmr_acc t = lane < W ? hipmr_wt[lane] : neutral;
+    t = hipmr_wave_scan(t, lane, neutral);
+    if (lane < W) hipmr_wt[lane] = t;
   }
   __syncthreads();
   const hipmr_acc up = __shfl_up(x, 1, 64);
-  hipmr_acc run = lane == 0 ? hipmr_neutral : up;
-  if (w > 0) run = hipmr_combine(hipmr_wt[w - 1], run);
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (k < per && t0 + k < hipmr_waves) {
-      hipmr_prefix[t0 + k] = run;
-      run = hipmr_combine(run, v[k]);
-    }
-  }
+  hipmr_acc r = lane == 0 ? neutral : up;
+  if (w > 0) r = hipmr_combine(hipmr_wt[w - 1], r);
+  *total = hipmr_wt[W - 1];
+  return r;
+}
+
+extern "C" __global__ void __launch_bounds__(1024)
+@@KNAME@@(const hipmr_acc* __restrict__ hipmr_partial, long long hipmr_waves,
+          hipmr_acc* __restrict__ hipmr_prefix, hipmr_acc* __restrict__ hipmr_btot, int hipmr_top)
+{
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  // hipmr_top == 0: block b scans totals [1024 b, 1024 b + 1024);
+  // hipmr_top == 1: the single block scans the block totals in place
+  const long long k = (long long)blockIdx.x * 1024 + threadIdx.x;
+  const hipmr_acc* src = hipmr_top ? hipmr_btot : hipmr_partial;
+  hipmr_acc* dst = hipmr_top ? hipmr_btot : hipmr_prefix;
+  const long long count = hipmr_top ? (hipmr_waves + 1023) / 1024 : hipmr_waves;
+  const hipmr_acc v = k < count ? src[k] : hipmr_neutral;
+  hipmr_acc total;
+  const hipmr_acc r = hipmr_block_exclusive<1024>(v, hipmr_neutral, &total);
+  __syncthreads();                              // every read of src precedes the writes
+  if (k < count) dst[k] = r;
+  if (!hipmr_top && threadIdx.x == 0) hipmr_btot[blockIdx.x] = total;
 }
 )HIP";
 
 // Pass 3: each wave rescans its range from its prefix and writes the outputs.
-// Two register sets of chunks alternate between passes, so the loads of the
-// next pass are in flight while the current pass is scanned and stored.
 const char* kScanDown = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head, int hipmr_passes,
           long long hipmr_waves, const hipmr_acc* __restrict__ hipmr_prefix,
-          hipmr_acc* __restrict__ hipmr_out, int hipmr_exclusive)
+          const hipmr_acc* __restrict__ hipmr_bpre, hipmr_acc* __restrict__ hipmr_out,
+          int hipmr_exclusive)
 {
   typedef @@IDX@@ hipmr_idx;
   constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
@@ -1133,7 +1133,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   const long long hipmr_c = hipmr_sub * HIPMR_U * hipmr_passes;
   const long long hipmr_b0 = hipmr_h + hipmr_w * hipmr_c;
   const long long hipmr_e = hipmr_b0 + hipmr_c < hipmr_n ? hipmr_b0 + hipmr_c : hipmr_n;
-  hipmr_acc hipmr_carry = hipmr_prefix[hipmr_w];
+  hipmr_acc hipmr_carry = hipmr_combine(hipmr_bpre[hipmr_w >> 10], hipmr_prefix[hipmr_w]);
   if (hipmr_w == 0 && hipmr_h > 0) {            // the unaligned head, one element per lane
     hipmr_acc hipmr_v = hipmr_neutral;
     if (hipmr_lane < hipmr_h) {
@@ -1147,50 +1147,25 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
                                               : hipmr_combine(hipmr_carry, hipmr_x);
     hipmr_carry = hipmr_combine(hipmr_carry, __shfl(hipmr_x, 63, 64));
   }
-  @@DECL_PACKS@@
-  @@DECL_PACKS_Q@@
-  long long hipmr_pb = hipmr_b0;
-#pragma unroll
-  for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
-    const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
-    if (hipmr_off + HIPMR_V <= hipmr_e) {
-      @@LOADS@@
-    }
-  }
-  for (int hipmr_p = 0; hipmr_p < hipmr_passes; hipmr_p += 2) {
-    hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
+  for (int hipmr_p = 0; hipmr_p < hipmr_passes; ++hipmr_p) {
+    const long long hipmr_pb = hipmr_b0 + (long long)hipmr_p * hipmr_sub * HIPMR_U;
     if (hipmr_pb >= hipmr_e) break;
-    {
-      const long long hipmr_nb = hipmr_pb + hipmr_sub * HIPMR_U;     // prefetch the next pass
+    @@DECL_PACKS@@
 #pragma unroll
-      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
-        const long long hipmr_off = hipmr_nb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
-        if (hipmr_off + HIPMR_V <= hipmr_e) {
-          @@LOADS_Q@@
-        }
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_off = hipmr_pb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
+      if (hipmr_off + HIPMR_V <= hipmr_e) {
+        @@LOADS@@
       }
     }
     @@PASS_P@@
-    hipmr_pb += hipmr_sub * HIPMR_U;
-    if (hipmr_pb >= hipmr_e) break;
-    {
-      const long long hipmr_nb = hipmr_pb + hipmr_sub * HIPMR_U;
-#pragma unroll
-      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
-        const long long hipmr_off = hipmr_nb + hipmr_sub * hipmr_u + (long long)hipmr_lane * HIPMR_V;
-        if (hipmr_off + HIPMR_V <= hipmr_e) {
-          @@LOADS@@
-        }
-      }
-    }
-    @@PASS_Q@@
   }
 }
 )HIP";
 
-// One pass of pass 3 over the chunks of one register set (@@VMAPX@@ reads
-// them): per sub-tile, the lane's inclusive prefixes of its V elements, a
-// wave scan of the lane totals, the outputs, the carry.
+// One pass of pass 3 over the chunks in registers (@@VMAPX@@ reads them):
+// per sub-tile, the lane's inclusive prefixes of its V elements, a wave scan
+// of the lane totals, the outputs, the carry.
 const char* kScanDownPass = R"HIP(
 #pragma unroll
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
@@ -1339,15 +1314,9 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
         loads.clear();
     }
     if (spec.kind == KernelKind::ScanDownVector || spec.kind == KernelKind::ScanDownScalar) {
-        // the second register set of chunks (prefetch of the next pass)
-        auto q = [](std::string t) { replace_all(t, "hipmr_p_", "hipmr_q_"); return t; };
-        std::string pass_p = kScanDownPass, pass_q = kScanDownPass;
+        std::string pass_p = kScanDownPass;
         replace_all(pass_p, "@@VMAPX@@", vector_text);
-        replace_all(pass_q, "@@VMAPX@@", q(vector_text));
         replace_all(body, "@@PASS_P@@", pass_p);
-        replace_all(body, "@@PASS_Q@@", pass_q);
-        replace_all(body, "@@DECL_PACKS_Q@@", q(decl_packs));
-        replace_all(body, "@@LOADS_Q@@", q(loads));
     }
 
     replace_all(body, "@@PARAMS@@", params);

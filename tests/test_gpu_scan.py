@@ -33,13 +33,18 @@ def run_scan(k, combine, neutral, n, args, out_dtype, dev, exclusive=False, out_
 
 def float_depth(n, vec=4, ipt=4):
     """Longest chain of float combinations on one output's path: wave totals
-    (V P sequential + U fold + 6 butterfly), their scan (2 runs of `per` + 6 +
-    4 + 1) and the rescan (U P carries + 6 + 1 + V + 1)."""
+    (V P_up sequential per accumulator + the pairwise fold of the pass-1
+    accumulators + 6 butterfly), the two-level scan of the totals (2 x (6 +
+    4 + 1)), the block prefix (1) and the rescan (U P carries + 6 + 1 + V +
+    1)."""
     sub = 64 * vec * ipt
-    passes = max(1, -(-n // (sub * 16384)))
-    waves = max(1, -(-n // (sub * passes)))
-    per = -(-waves // 1024)
-    return (vec * passes + ipt + 6) + (2 * per + 11) + (ipt * passes + vec + 8)
+    passes = max(1, -(-n // (sub * 65536)))
+    up = min(ipt, 4)
+    while ipt % up:
+        up -= 1
+    passes_up = passes * (ipt // up)
+    fold = max(0, (up - 1).bit_length())
+    return (vec * passes_up + fold + 6) + 22 + 1 + (ipt * passes + vec + 8)
 
 
 def assert_float_scan(g, r, n, what, vec=4, ipt=4):
