@@ -27,7 +27,8 @@ from __future__ import annotations
 from . import hipmr as _hm
 
 SPMV = ("float *q, const float *p, int nx",
-        "q[i] = 4.0f*p[i] - (i % nx != 0 ? p[i-1] : 0.0f) - (i % nx != nx - 1 ? p[i+1] : 0.0f)"
+        "int c = i % nx; "
+        "q[i] = 4.0f*p[i] - (c != 0 ? p[i-1] : 0.0f) - (c != nx - 1 ? p[i+1] : 0.0f)"
         " - (i >= nx ? p[i-nx] : 0.0f) - (i + nx < n ? p[i+nx] : 0.0f)")
 DOT = ("float: const float *p, const float *q", "p[i]*q[i]")
 ALPHA = ("float *alpha, const float *rr, const float *pq", "alpha[i] = rr[i] / pq[i]")

@@ -411,6 +411,10 @@ hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void* const* args,
     bool vector = h->prog.info.vectorizable && !cfg.force_scalar;
     if (vector) head = common_head(h, args, cfg.vec);
     if (head < 0) vector = false;
+    // the one-element kernel does best as a grid-stride loop over a resident
+    // grid (measured on MI355X with a five-point stencil: 30 us against 37 us
+    // for one element per thread over a full grid)
+    if (!vector && !(cfgp && (cfgp->blocks_per_cu || cfgp->grid))) cfg.blocks_per_cu = kEwScalarBlocksPerCu;
     KernelSpec spec;
     spec.kind = vector ? KernelKind::EwVector : KernelKind::EwScalar;
     spec.idx64 = n >= (int64_t(1) << 31);

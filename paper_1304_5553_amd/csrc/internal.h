@@ -32,6 +32,7 @@ constexpr size_t kWorkspaceBytes = kScaleOffset + 256;
 // in flight per thread and array); elementwise kernels, which mix reads and
 // writes, do best as one pass over a full grid (one chunk per thread).
 constexpr int kEwBlock = 256, kEwIpt = 1, kEwBlocksPerCu = 1 << 20;
+constexpr int kEwScalarBlocksPerCu = 32;     // one-element elementwise kernels
 constexpr int kRedBlock = 256, kRedIpt = 4, kRedBlocksPerCu = 2;
 
 hipmr_status resolve_cfg(const hipmr_launch_config* c, int block, int ipt, int vec,
