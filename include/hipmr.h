@@ -115,6 +115,9 @@ typedef struct hipmr_launch_config {
 #define HIPMR_CFG_TEMPORAL_STORES 16  /* streaming loads, ordinary stores                    */
 #define HIPMR_CFG_SEG_GLOBAL      32  /* segmented: read the tile table from global memory
                                          even when it would fit in LDS                       */
+/* Streaming stores apply to chunks of at most 16 bytes per lane; a wider
+ * chunk (e.g. four 64-bit results) leaves in several instructions that each
+ * fill half lines, and is stored temporally so that the L2 merges them. */
 
 /* ------------------------------------------------------------------ core */
 

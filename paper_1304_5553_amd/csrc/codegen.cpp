@@ -212,6 +212,10 @@ __device__ __forceinline__ void hipmr_load(hipmr_pack_fp8ro<N>& p, const hipmr_f
   __builtin_memcpy(&p, &raw, N);
 }
 
+// A chunk wider than 16 bytes leaves in several store instructions, each
+// covering every other 16 bytes of the lanes' lines: streaming stores would
+// write those half lines out unmerged, so wide chunks are stored temporally
+// (the L2 merges them).
 template <bool NT, typename T, int N>
 __device__ __forceinline__ void hipmr_store(T* dst, const hipmr_pack<T, N>& p) {
   constexpr int B = (int)sizeof(T) * N;
@@ -222,7 +226,7 @@ __device__ __forceinline__ void hipmr_store(T* dst, const hipmr_pack<T, N>& p) {
   word* d = reinterpret_cast<word*>(dst);
 #pragma unroll
   for (int k = 0; k < B / W; ++k) {
-    if constexpr (NT) __builtin_nontemporal_store(tmp[k], d + k);
+    if constexpr (NT && B <= 16) __builtin_nontemporal_store(tmp[k], d + k);
     else d[k] = tmp[k];
   }
 }

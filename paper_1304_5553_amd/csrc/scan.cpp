@@ -103,12 +103,6 @@ hipmr_status hipmr_scan(hipmr_handle h, const char* combine, const char* neutral
         cfg.vec = 1;
         head = 0;
     }
-    // A lane stores V results per chunk; wider than 16 bytes, one store
-    // instruction covers every other 16 bytes of a line, which streaming
-    // (non-temporal) stores write out unmerged: keep such stores temporal.
-    const uint32_t flags = cfgp ? cfgp->flags : 0u;
-    if (!(flags & (HIPMR_CFG_TEMPORAL | HIPMR_CFG_NONTEMPORAL | HIPMR_CFG_TEMPORAL_STORES)))
-        cfg.nt_stores = (long long)cfg.vec * dtype_size(h->prog.sig.result) <= 16;
     const long long n64 = n;
     head = std::min<long long>(head, n64);
     const long long body = n64 - head;
