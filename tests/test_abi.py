@@ -160,3 +160,12 @@ def test_prepare_reduce_builds_without_a_gpu():
 
 def test_selftest_compiles_every_template():
     assert hm.selftest_compile() >= 30
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # the product path has no CPU or torch fallback: without the built
+    # library every call raises
+    monkeypatch.setattr(hm.hipmr, "LIB_PATH", "/nonexistent/libhipmr.so")
+    monkeypatch.setattr(hm.hipmr, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        hm.compile("z[i] = x[i]", "float *z, const float *x")
