@@ -188,19 +188,17 @@ __device__ __forceinline__ void hipmr_load(hipmr_pack<T, N>& p, const T* src) {
   __builtin_memcpy(&p, tmp, B);
 }
 
-// A read-only chunk of N FP8 values kept as 32-bit words: element j decodes
-// with the byte-select form of the conversion instruction (one instruction
-// per element, no byte extraction).
+// A read-only chunk of N FP8 values kept as 32-bit words: elements 2k and
+// 2k + 1 decode together with the packed conversion instruction (one
+// instruction per pair; the pair's two reads share it), no byte extraction.
+typedef float hipmr_f32x2 __attribute__((ext_vector_type(2)));
 template <int N> struct hipmr_fp8_words {
   unsigned int w[N / 4];
   __device__ __forceinline__ float operator[](int j) const {
     const int word = (int)w[j >> 2];
-    switch (j & 3) {
-      case 0: return __builtin_amdgcn_cvt_f32_fp8(word, 0);
-      case 1: return __builtin_amdgcn_cvt_f32_fp8(word, 1);
-      case 2: return __builtin_amdgcn_cvt_f32_fp8(word, 2);
-      default: return __builtin_amdgcn_cvt_f32_fp8(word, 3);
-    }
+    const hipmr_f32x2 pair = (j & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(word, true)
+                                     : __builtin_amdgcn_cvt_pk_f32_fp8(word, false);
+    return (j & 1) ? pair.y : pair.x;
   }
 };
 template <int N> struct hipmr_pack_fp8ro { hipmr_fp8_words<N> v; };
@@ -1364,14 +1362,15 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     if (comp) src << kCompHelpers;
     if (seg) src << kSegHelpers;
     if (scan) src << kScanHelpers;
-    // the symbol carries a hash of everything that shapes the kernel
-    std::string unnamed = cbody + "\n" + body;
-    std::string key = sha256_hex(unnamed.data(), unnamed.size());
-    std::string sym = prog.name + "_" + tag + "_" + key.substr(0, 8);
-    replace_all(body, "@@KNAME@@", sym);
+    // the symbol carries a hash of the whole source (prelude and helpers
+    // included), so any change to the generated code renames the kernel
     src << body;
+    std::string text = src.str();
+    std::string key = sha256_hex(text.data(), text.size());
+    std::string sym = prog.name + "_" + tag + "_" + key.substr(0, 8);
+    replace_all(text, "@@KNAME@@", sym);
     if (symbol) *symbol = sym;
-    return src.str();
+    return text;
 }
 
 }  // namespace hipmr
