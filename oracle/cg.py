@@ -36,11 +36,11 @@ def laplace5(p, nx: int) -> np.ndarray:
     return q.ravel()
 
 
-def cg(b, nx: int, iters: int, x0=None):
+def cg(b, nx: int, iters: int, x0=None, keep_directions=False):
     """`iters` conjugate-gradient steps from x0 (zero by default).  Returns
     the iterate and the histories of r . r (entry k before step k, so
-    iters + 1 values), alpha and beta, and the search directions' A-products
-    p_k . A p_k."""
+    iters + 1 values), alpha and beta, the search directions' A-products
+    p_k . A p_k, and (with keep_directions) the directions themselves."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     r = b - laplace5(x, nx)
@@ -55,7 +55,8 @@ def cg(b, nx: int, iters: int, x0=None):
         r = r - alpha * q
         rr_new = float(r @ r)
         beta = rr_new / rr
-        hist["p"].append(p.copy())
+        if keep_directions:
+            hist["p"].append(p.copy())
         p = r + beta * p
         rr = rr_new
         hist["rr"].append(rr)

@@ -112,14 +112,15 @@ def test_graph_replay_equals_eager(dev):
             _ = (bd * 2).sum().item()
 
 
-def test_cg_at_scale_tracks_the_oracle(dev):
-    nx, ny = 1024, 768
+@pytest.mark.parametrize("nx,ny,iters", [(1024, 768, 40), (4096, 4096, 30)])
+def test_cg_at_scale_tracks_the_oracle(dev, nx, ny, iters):
+    # the 4096 x 4096 grid is the size the benchmark times
     _, b = make_problem(nx, ny, 7)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         solver = hcg.PoissonCG(nx, ny, device=dev, stream=stream)
-        solver.solve(dev_array(b), 40)
+        solver.solve(dev_array(b), iters)
         stream.synchronize()
         rr = float(host_bits(solver.s)[0])
-    _, hist = oracle.cg(b.astype(np.float64), nx, 40)
+    _, hist = oracle.cg(b.astype(np.float64), nx, iters)
     assert abs(rr / hist["rr"][-1] - 1) < 1e-2, (rr, hist["rr"][-1])

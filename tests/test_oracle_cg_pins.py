@@ -42,7 +42,7 @@ def test_cg_invariants_orthogonal_residuals_conjugate_directions():
     rng = np.random.default_rng(2)
     b = rng.uniform(-1, 1, nx * ny)
     A = laplace_matrix(nx, ny)
-    _, hist = oracle.cg(b, nx, 12)
+    _, hist = oracle.cg(b, nx, 12, keep_directions=True)
     P = np.array(hist["p"])                      # directions p_0 .. p_11
     G = P @ (A @ P.T)                            # p_j . A p_k
     d = np.sqrt(np.outer(np.diag(G), np.diag(G)))
