@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="precision,batched,served,scan,cg,lazy",
+    p.add_argument("--extensions", default="dot,precision,batched,served,scan,cg,lazy",
                    help="comma list of the extension measurements to run "
-                        "(precision, batched, served, scan, cg, lazy)")
+                        "(dot, precision, batched, served, scan, cg, lazy)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -113,6 +113,43 @@ def _time_ms(torch, fn, reps, stream):
         b.record(stream)
     torch.cuda.synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def bench_dot(torch, hm, workloads, dev, stream, reps=200):
+    """The small dot product x . y over 2^20 float32 (8.4 MB, about 1 us of
+    HBM traffic): a launch-bound call, reported in microseconds.  `async_us`
+    is the per-call time of back-to-back calls (HIP events around all of
+    them); `synced_us` the median of single calls each followed by a host
+    synchronisation (submission + both kernels + the wait)."""
+    x, y = workloads.dot_1m()
+    xd, yd = (torch.from_numpy(a).to(dev) for a in (x, y))
+    out = torch.empty((), dtype=torch.float32, device=dev)
+    k = hm.compile("x[i]*y[i]", "float: const float *x, const float *y", name="dot_1m")
+    from paper_1304_5553_amd import hipmr as binding
+    ws = binding.workspace(binding.reduce_workspace_bytes(k, x.size), dev, stream.cuda_stream)
+    call = lambda: hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], out, workspace_buf=ws)
+    for _ in range(20):
+        call()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        call()
+    b.record(stream)
+    torch.cuda.synchronize()
+    async_us = a.elapsed_time(b) * 1e3 / reps
+    synced = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        synced.append((time.perf_counter() - t0) * 1e6)
+    gpu_ms = _time_ms(torch, call, reps, stream)
+    return {"n": int(x.size), "bytes": 8 * int(x.size), "async_us": round(async_us, 2),
+            "synced_us_p50": round(float(np.median(synced)), 2),
+            "event_us_p50": round(gpu_ms * 1e3, 2),
+            "GB/s_async": round(8 * x.size / async_us / 1e3, 1),
+            "note": "launch-bound: 8.4 MB is about 1 us of HBM traffic; GB/s is not a roofline claim"}
 
 
 def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
@@ -528,6 +565,9 @@ def main():
     if ext:
         del xd, yd, kd, z
         torch.cuda.empty_cache()
+    if "dot" in ext:
+        line["dot"] = bench_dot(torch, hm, workloads, dev, stream)
+        print("dot done", file=sys.stderr, flush=True)
     if "precision" in ext:
         line["precision"] = bench_precision(torch, hm, workloads, dev, stream)
         print("precision done", file=sys.stderr, flush=True)

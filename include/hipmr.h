@@ -262,9 +262,10 @@ size_t hipmr_scan_workspace_bytes(hipmr_handle h, int64_t n);
  * Three launches on `stream`: every wave folds a contiguous range, one block
  * scans the wave totals, every wave rescans its range from its prefix.  The
  * order of combination depends only on n, alignment and geometry (bitwise
- * repeatable).  16-byte accesses when every array and out share one
- * alignment and the map reads arrays only as name[i]; one element at a time
- * otherwise.  n == 0 writes nothing.  Errors: E_INVALID (NULL, exclusive not
+ * repeatable).  Chunked accesses when every array and out share one
+ * alignment and the map reads arrays only as name[i] (by default 16 bytes of
+ * the narrowest input, but at most 16 bytes of output, per lane); one
+ * element at a time otherwise.  n == 0 writes nothing.  Errors: E_INVALID (NULL, exclusive not
  * 0/1), E_MISMATCH (elementwise handle), E_WORKSPACE, E_PARSE / E_COMPILE
  * (combine or neutral), E_HIP. */
 hipmr_status hipmr_scan(hipmr_handle h, const char *combine_op, const char *neutral, int64_t n,
@@ -372,8 +373,14 @@ typedef struct hipmr_server_config {
                                     elements, 2-8 times that in jobs of over 2^23 / 2^24
                                     elements, so that no job has more than 8192); 0: 2^18         */
     int32_t blocks_per_cu;       /* persistent grid of the tile kernel; 0: 8                        */
-    uint64_t max_batch_bytes;    /* input bytes per batch of two or more jobs (a larger job runs
-                                    alone), so small jobs do not wait on large ones; 0: 16 MiB     */
+    uint64_t max_batch_bytes;    /* input bytes per batch of two or more jobs; 0: 16 MiB           */
+    uint64_t solo_bytes;         /* a job of more input bytes runs in a batch of its own, and
+                                    smaller jobs are packed past it, so small jobs never wait on
+                                    a large one's tiles (<= max_batch_bytes); 0: 4 MiB            */
+    int32_t batch_backlog;       /* jobs are packed together only while more than this many wait
+                                    per free stream (a shorter queue runs one job per stream, as
+                                    the one-launch-pair-per-job loop does); 0: 8                   */
+    int32_t reserved;            /* 0                                                               */
 } hipmr_server_config;
 
 typedef struct hipmr_completion {
@@ -394,8 +401,11 @@ size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
 /* Serving extension of the map-reduce: starts a request loop on a host thread
  * for the current device.  The loop releases arrivals, admits them in arrival
  * order while the bytes of admitted, unfinished jobs stay within the budget,
- * packs admitted jobs into one batch per free stream (continuous batching:
- * jobs that arrive while others run join the next batch on a free stream) and
+ * spreads admitted jobs over the free streams, one batch per stream (continuous
+ * batching: jobs that arrive while others run join the next batch on a free
+ * stream; one job per free stream while at most batch_backlog jobs per free
+ * stream wait, else ceil(waiting / free streams) jobs per batch; a job over
+ * solo_bytes runs alone and small jobs are packed past it) and
  * launches it as two run-time compiled kernels: a persistent kernel whose
  * waves take tiles of any job (wave-uniform switch over template x dtype) and
  * one block per job folding its tiles in a fixed order.  A job's tiles depend

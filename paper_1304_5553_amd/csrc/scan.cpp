@@ -93,8 +93,15 @@ hipmr_status hipmr_scan(hipmr_handle h, const char* combine, const char* neutral
     if (!out) return fail(HIPMR_E_INVALID, "out is NULL");
     if (!workspace || workspace_bytes < hipmr_scan_workspace_bytes(h, n))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_scan_workspace_bytes()");
+    // Default chunk: 16 bytes of the narrowest input, but at most 16 bytes of
+    // output per lane, so that each store instruction of a wave writes one
+    // contiguous run; a narrower chunk takes more sub-tiles per pass (at most
+    // 8) to keep the loads in flight.
+    const int out_size = dtype_size(h->prog.sig.result);
+    const int dvec = std::min(h->default_vec, std::max(1, 16 / out_size));
+    const int dipt = std::min(8, kScanIpt * (h->default_vec / dvec));
     LaunchCfg cfg;
-    st = resolve_cfg(cfgp, kScanBlock, kScanIpt, h->default_vec, 1, &cfg);
+    st = resolve_cfg(cfgp, kScanBlock, dipt, dvec, 1, &cfg);
     if (st != HIPMR_OK) return st;
 
     long long head = h->prog.info.vectorizable && !cfg.force_scalar ? scan_head(h, args, out, cfg.vec) : -1;

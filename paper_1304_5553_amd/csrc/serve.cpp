@@ -9,8 +9,11 @@
 //   - arrivals are released at their scheduled time;
 //   - they are admitted while the bytes of unfinished jobs stay within the HBM
 //     budget;
-//   - admitted jobs are packed into one batch per free stream slot (up to k
-//     batches in flight);
+//   - admitted jobs go to the free stream slots, one batch per slot (up to k
+//     batches in flight): one job per slot while the queue is short, batches
+//     of ceil(waiting / free slots) once it is long, so batches grow with the
+//     backlog; a large job runs in a batch of its own and small jobs are
+//     packed past it;
 //   - a batch is two launches of run-time compiled kernels:
 //       1. a persistent kernel whose waves take fixed-size tiles of any job in
 //          the batch (a wave-uniform switch over template x dtype);
@@ -33,6 +36,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <vector>
 #include <thread>
 
 #include "internal.h"
@@ -45,6 +49,7 @@ constexpr int kServeBlock = 256;          // tile kernels: 4 waves, one tile per
 constexpr int kFinBlock = 1024;           // final fold: one block per job
 constexpr int kMaxBatchJobs = 4096;      // jobs per batch (their tile offsets are staged in LDS)
 constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
+constexpr int kMaxSkipped = 64;          // large jobs one batch of small ones may be packed past
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
@@ -421,6 +426,8 @@ hipmr_server_config resolved(const hipmr_server_config* in) {
     if (c.max_batch_tiles == 0) c.max_batch_tiles = 1 << 18;
     if (c.blocks_per_cu == 0) c.blocks_per_cu = 8;
     if (c.max_batch_bytes == 0) c.max_batch_bytes = 16ull << 20;
+    if (c.solo_bytes == 0) c.solo_bytes = std::min<uint64_t>(4ull << 20, c.max_batch_bytes);
+    if (c.batch_backlog == 0) c.batch_backlog = 8;
     return c;
 }
 
@@ -482,6 +489,7 @@ struct hipmr_server {
     std::condition_variable cv_work, cv_done;
     std::deque<Pending> incoming;       // submitted, not yet seen by the loop
     std::deque<Pending> waiting;        // arrived, not yet admitted (loop thread only)
+    std::vector<Pending> skipped;       // large jobs a batch of small ones was packed past
     std::vector<hipmr_completion> finished;   // for poll
     uint64_t next_ticket = 1;
     uint64_t admitted = 0;              // bytes of admitted, unfinished jobs
@@ -625,22 +633,54 @@ struct hipmr_server {
             s.busy = false;
             progressed = true;
         }
-        // admission + packing into free slots
+        // admission + packing into free slots.  While at most batch_backlog
+        // jobs per free slot wait, each free slot takes one job, as the
+        // one-launch-pair-per-job loop would (packing a short queue into one
+        // stream measured a longer p99 than spreading it); a longer queue is
+        // spread over the free slots, ceil(waiting / free) jobs per batch, so
+        // batches grow with the backlog and drain it.  A job of more than solo_bytes runs
+        // in a batch of its own; a batch of smaller jobs is packed past such
+        // jobs, which keep their places for the next free slot, so a small
+        // job never waits for a large one's tiles.  Admission keeps arrival
+        // order: packing stops at the first job, skipped or not, that does not
+        // fit the budget.
+        int free_slots = 0;
+        for (const Slot& s : slots) free_slots += !s.busy;
         for (Slot& s : slots) {
             if (s.busy || waiting.empty()) continue;
-            int tiles = 0;
-            uint64_t bytes = 0;
-            while (!waiting.empty() && (int)s.jobs.size() < cfg.max_batch_jobs) {
+            const size_t w = waiting.size();
+            const size_t quota = w <= (size_t)cfg.batch_backlog * free_slots ? 1 : (w + free_slots - 1) / free_slots;
+            --free_slots;
+            if (waiting.front().bytes > cfg.solo_bytes) {
                 const Pending& p = waiting.front();
                 if (admitted + p.bytes > cfg.hbm_budget_bytes) break;
-                if (!s.jobs.empty() &&
-                    (tiles + p.tiles > cfg.max_batch_tiles || bytes + p.bytes > cfg.max_batch_bytes))
-                    break;
                 admitted += p.bytes;
-                tiles += p.tiles;
-                bytes += p.bytes;
                 s.jobs.push_back(p);
                 waiting.pop_front();
+            } else {
+                int tiles = 0;
+                uint64_t bytes = 0;
+                skipped.clear();
+                while (!waiting.empty() && (int)s.jobs.size() < cfg.max_batch_jobs &&
+                       s.jobs.size() < quota) {
+                    const Pending& p = waiting.front();
+                    if (admitted + p.bytes > cfg.hbm_budget_bytes) break;
+                    if (p.bytes > cfg.solo_bytes) {
+                        if ((int)skipped.size() == kMaxSkipped) break;
+                        skipped.push_back(p);
+                        waiting.pop_front();
+                        continue;
+                    }
+                    if (!s.jobs.empty() &&
+                        (tiles + p.tiles > cfg.max_batch_tiles || bytes + p.bytes > cfg.max_batch_bytes))
+                        break;
+                    admitted += p.bytes;
+                    tiles += p.tiles;
+                    bytes += p.bytes;
+                    s.jobs.push_back(p);
+                    waiting.pop_front();
+                }
+                for (auto it = skipped.rbegin(); it != skipped.rend(); ++it) waiting.push_front(*it);
             }
             if (s.jobs.empty()) break;       // budget full: wait for completions
             hipmr_status st = launch_batch(s);
@@ -727,6 +767,9 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
     if (c.max_batch_jobs < 1 || c.max_batch_jobs > kMaxBatchJobs)
         return fail(HIPMR_E_INVALID, "max_batch_jobs must be in [1, 4096]");
     if (c.max_batch_tiles < 1 || c.blocks_per_cu < 1) return fail(HIPMR_E_INVALID, "bad batch limits");
+    if (c.batch_backlog < 0) return fail(HIPMR_E_INVALID, "batch_backlog must be >= 0");
+    if (c.solo_bytes > c.max_batch_bytes)
+        return fail(HIPMR_E_INVALID, "solo_bytes must not exceed max_batch_bytes");
     if (!workspace || workspace_bytes < hipmr_server_workspace_bytes(&c))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_server_workspace_bytes()");
     auto s = std::make_unique<hipmr_server>();

@@ -600,7 +600,9 @@ JOB_NAMES = ["sum", "dot", "norm2", "max", "axpby_sum", "count_pos", "sumsq", "w
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("nstreams", ctypes.c_int32),
                 ("max_batch_jobs", ctypes.c_int32), ("max_batch_tiles", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64)]
+                ("blocks_per_cu", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64),
+                ("solo_bytes", ctypes.c_uint64), ("batch_backlog", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def _sjob_dtype():
@@ -625,12 +627,12 @@ class Server:
     ``Server.JOB`` (device pointers as integers)."""
 
     def __init__(self, hbm_budget_bytes=0, nstreams=0, max_batch_jobs=0, max_batch_tiles=0,
-                 blocks_per_cu=0, max_batch_bytes=0, device=None):
+                 blocks_per_cu=0, max_batch_bytes=0, solo_bytes=0, batch_backlog=0, device=None):
         import torch
         self.JOB = _sjob_dtype()
         self.COMPLETION = _completion_dtype()
         self.cfg = ServerConfig(hbm_budget_bytes, nstreams, max_batch_jobs, max_batch_tiles,
-                                blocks_per_cu, max_batch_bytes)
+                                blocks_per_cu, max_batch_bytes, solo_bytes, batch_backlog, 0)
         nbytes = lib().hipmr_server_workspace_bytes(ctypes.byref(self.cfg))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8,
                                      device=device or torch.device("cuda"))

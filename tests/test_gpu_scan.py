@@ -47,6 +47,13 @@ def float_depth(n, vec=4, ipt=4):
     return (vec * passes_up + fold + 6) + 22 + 1 + (ipt * passes + vec + 8)
 
 
+def default_geometry(in_size, out_size):
+    """(V, U) the library picks by default: 16 bytes of the narrowest input,
+    at most 16 bytes of output per lane, up to 8 sub-tiles per pass."""
+    vec = min(16 // in_size, max(1, 16 // out_size))
+    return vec, min(8, 4 * ((16 // in_size) // vec))
+
+
 def assert_float_scan(g, r, n, what, vec=4, ipt=4):
     d = float_depth(n, vec, ipt)
     tol = d * U24 * r.abs_prefix + 2 * r.err_prefix + 1e-30
@@ -127,7 +134,8 @@ def test_low_precision_input_scan(dev, fmt, torch_dt):
     h = hm.compile("x[i]", sig, name="scan_lowp")
     g = host_bits(run_scan(h, "a+b", "0", n, [dev_array(bits, fmt)], torch.float32, dev))
     r = oracle.scan(sig, "x[i]", "a+b", "0", n, [bits])
-    assert_float_scan(g.astype(np.float64), r, n, fmt)
+    vec, ipt = default_geometry(bits.dtype.itemsize, 4)
+    assert_float_scan(g.astype(np.float64), r, n, fmt, vec=vec, ipt=ipt)
     # max of the same values is exact
     g = host_bits(run_scan(h, "max", "-INFINITY", n, [dev_array(bits, fmt)], torch.float32, dev))
     r = oracle.scan(sig, "x[i]", "max", "-INFINITY", n, [bits])

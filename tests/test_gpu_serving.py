@@ -90,10 +90,11 @@ def oracle_check(k, got, sched, pool):
 @pytest.fixture(scope="module")
 def mix(dev, pool):
     # 100k jobs/s on two streams: arrivals outpace single-job service, so jobs
-    # that arrive while others run are packed into the next free slot
+    # that arrive while others run are packed into the next free slot (any
+    # queue longer than the free slots is packed)
     sched = workloads.serving_schedule(100000, 0.005, pool_n=POOL_N, log2_max=20)
     out = torch.full((len(sched["n"]),), float("nan"), dtype=torch.float64, device=dev)
-    server = hm.Server(nstreams=2, max_batch_jobs=1024)
+    server = hm.Server(nstreams=2, max_batch_jobs=1024, batch_backlog=1)
     done = server.run_schedule(make_jobs(server, sched, pool, out))
     torch.cuda.synchronize()
     server.close()
@@ -191,3 +192,51 @@ def test_burst_packs_large_batches(dev, pool, max_jobs):
     got = out.cpu().numpy()
     for k in range(len(got)):
         oracle_check(k, float(got[k]), sched, pool)
+
+
+def test_large_jobs_run_alone_and_small_ones_pass_them(dev, pool):
+    # a burst on one stream alternating jobs over and under solo_bytes: every
+    # large job runs in a batch of its own, the small ones are packed together
+    # past them, and every result matches the oracle
+    sched = workloads.serving_schedule(50000, 0.004, pool_n=POOL_N, log2_min=10, log2_max=12)
+    m = len(sched["n"])
+    sched["arrival_ns"][:] = 0
+    sched["n"][::3] = POOL_N // 2                  # 1 MiB of bfloat16 / 2 MiB of float32 per array
+    sched["offset"][::3] = np.minimum(sched["offset"][::3], POOL_N - POOL_N // 2)
+    out = torch.full((m,), float("nan"), dtype=torch.float64, device=dev)
+    solo = 1 << 20
+    server = hm.Server(nstreams=1, max_batch_jobs=1024, solo_bytes=solo)
+    jobs = make_jobs(server, sched, pool, out)
+    done = server.run_schedule(jobs)
+    torch.cuda.synchronize()
+    server.close()
+    assert m > 100 and np.all(done["status"] == 0)
+    large = np.zeros(m, bool)
+    large[::3] = True
+    assert np.all(done["batch_jobs"][large] == 1)
+    assert int(np.max(done["batch_jobs"][~large])) > 10
+    # the first small jobs are not held back behind the large ones
+    first_small = np.nonzero(~large)[0][:10]
+    assert np.all(done["done_ns"][first_small] <= np.sort(done["done_ns"][large])[1])
+    got = out.cpu().numpy()
+    for k in range(m):
+        oracle_check(k, float(got[k]), sched, pool)
+
+
+def test_short_queue_runs_one_job_per_stream(dev, pool):
+    # bursts of 4 jobs on 4 streams wait at most batch_backlog per free stream:
+    # each job gets a stream of its own; bursts of 40 are packed
+    sched = workloads.serving_schedule(50000, 0.004, pool_n=POOL_N, log2_max=14)
+    m = len(sched["n"])
+    for burst, packed in ((4, False), (40, True)):
+        sched["arrival_ns"] = (np.arange(m) // burst) * 300_000
+        out = torch.full((m,), float("nan"), dtype=torch.float64, device=dev)
+        server = hm.Server(nstreams=4, max_batch_jobs=1024, batch_backlog=8)
+        done = server.run_schedule(make_jobs(server, sched, pool, out))
+        torch.cuda.synchronize()
+        server.close()
+        assert np.all(done["status"] == 0)
+        assert (int(np.max(done["batch_jobs"])) > 1) == packed, burst
+        got = out.cpu().numpy()
+        for k in range(0, m, 7):
+            oracle_check(k, float(got[k]), sched, pool)
