@@ -145,10 +145,20 @@ hipmr_status hipmr_compile_named(const char *expr, const char *dtypes, const cha
 
 /* Runs an elementwise handle over i in [0, n).  Section "Efficient Evaluation
  * of Element-wise Expressions" (one pass over all operands).  n == 0 enqueues
- * nothing.  Arrays must hold at least n elements (the caller checks lengths).
- * When every array is accessed only as name[i] and all array pointers share
- * one misalignment, the 16-byte-vector kernel runs (unaligned head and ragged
- * tail handled by scalar code); otherwise the one-element kernel.
+ * nothing.  Arrays accessed as name[i] or name[i +/- E] must hold at least n
+ * elements (the caller checks lengths); arrays read only at fixed indices
+ * (name[3]) need only hold those elements.
+ * The vector kernel runs when every array access is name[i], a fixed element,
+ * or a shifted read name[i + E] / name[i - E] of an array the statement does
+ * not write (E built from literals, scalar arguments, n, + - * / % and
+ * parentheses: the same distance for every i), and the name[i] arrays share
+ * one misalignment: 16-byte chunks for name[i] (unaligned head and ragged tail
+ * by scalar code), one unaligned chunk load per distinct shifted read, and,
+ * for chunks within the largest distance of either end, the statement one
+ * element at a time (its own guards apply there; shifted chunks are read only
+ * inside [0, n)).  With shifted reads, workgroups are renumbered so that each
+ * XCD (own L2) takes a contiguous run of chunks.  Otherwise the one-element
+ * kernel runs.
  * Errors: E_INVALID (n < 0, NULL args or array pointer), E_MISMATCH (reduce
  * handle), E_COMPILE / E_HIP. */
 hipmr_status hipmr_elementwise(hipmr_handle h, int64_t n, void *const *args, void *stream);

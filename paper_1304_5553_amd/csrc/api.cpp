@@ -17,7 +17,7 @@ namespace hipmr {
 int default_vec_for(const Signature& sig) {
     int min_size = 0;
     for (auto& a : sig.args)
-        if (chunked(a)) {
+        if (chunked(a) || a.shifted) {
             int s = dtype_size(a.dtype);
             if (min_size == 0 || s < min_size) min_size = s;
         }
@@ -637,6 +637,9 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         {"z[i] = sqrtf(x[i]*x[i] + y[i]*y[i])", "float *z, const float *x, const float *y", nullptr, nullptr},
         {"if (k[i] > 3) o[i] = x[i]; else o[i] += 1", "const int *k, const bfloat16 *x, half *o", nullptr, nullptr},
         {"q[i] = x[i + 1 < n ? i + 1 : i] * s", "fp8_e4m3 *q, const float *x, float s", nullptr, nullptr},
+        {"int c = i % nx; q[i] = 4.0f*p[i] - (c != 0 ? p[i-1] : 0.0f) - (i + nx < n ? p[i + nx] : 0.0f)",
+         "float *q, const float *p, int nx", nullptr, nullptr},
+        {"o[i] = 0.5f * (x[i + 2*k] + x[i - (k)])", "bfloat16 *o, const bfloat16 *x, long k", nullptr, nullptr},
         {"k[i] % 7 == 3", "long: const int *k", "a+b", "0"},
         {"x[i]*y[i]", "float: const float *x, const float *y", "a+b", "0"},
         {"x[i]", "float: const float *x", "max(a,b)", "-INFINITY"},

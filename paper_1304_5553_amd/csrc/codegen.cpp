@@ -337,6 +337,93 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
+// The vector elementwise kernel for statements with shifted reads
+// name[i + E]: per chunk, each distinct shifted read is one unaligned load of
+// V elements from name + off + E.  A chunk whose shifted loads would leave
+// [0, n) (within |E| of either end) runs the statement one element at a time
+// instead, with the statement's own guards.
+const char* kEwVectorShift = R"HIP(
+// 16 bytes at 4-byte alignment: one dwordx4 load (the memory system accepts
+// dword-aligned multi-dword accesses); narrower element types go by memcpy
+typedef unsigned int hipmr_u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+template <typename T, int N>
+__device__ __forceinline__ void hipmr_loadu(hipmr_pack<T, N>& p, const T* src) {
+  if constexpr (sizeof(p) % 16 == 0 && alignof(T) >= 4) {
+    hipmr_u32x4u w[sizeof(p) / 16];
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(p) / 16); ++k) w[k] = reinterpret_cast<const hipmr_u32x4u*>(src)[k];
+    __builtin_memcpy(&p, w, sizeof(p));
+  } else {
+    __builtin_memcpy(&p, src, sizeof(p));
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  @@SHIFT_INIT@@
+  const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / HIPMR_V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * HIPMR_V;
+  if (blockIdx.x == 0) {
+    if ((long long)threadIdx.x < hipmr_h) {
+      const hipmr_idx i = (hipmr_idx)threadIdx.x;
+      { @@STMT@@; }
+    }
+    if ((long long)threadIdx.x < hipmr_n - hipmr_t0) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_t0 + threadIdx.x);
+      { @@STMT@@; }
+    }
+  }
+  // XCD-aware order: workgroups go round-robin to the 8 XCDs, each with its
+  // own L2.  Renumbered, each XCD takes a contiguous run of chunks, so the
+  // neighbouring elements a shifted read reaches were loaded by the same XCD.
+  const unsigned hipmr_x = blockIdx.x % 8u, hipmr_q8 = gridDim.x / 8u, hipmr_r8 = gridDim.x % 8u;
+  const unsigned hipmr_bid = hipmr_x * hipmr_q8 + (hipmr_x < hipmr_r8 ? hipmr_x : hipmr_r8) + blockIdx.x / 8u;
+  const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
+  for (long long hipmr_c0 = (long long)hipmr_bid * (HIPMR_B * HIPMR_U) + threadIdx.x; hipmr_c0 < hipmr_nc;
+       hipmr_c0 += hipmr_step) {
+    @@DECL_PACKS@@
+    @@SHIFT_PACKS@@
+    bool hipmr_vec[HIPMR_U];
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
+      const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
+      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_off + hipmr_smin >= 0 &&
+                           hipmr_off + HIPMR_V + hipmr_smax <= hipmr_n;
+      if (hipmr_vec[hipmr_u]) {
+        @@LOADS@@
+        @@SHIFT_LOADS@@
+      }
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
+      const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
+      if (hipmr_vec[hipmr_u]) {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          { @@VSTMT@@; }
+        }
+        @@STORES@@
+      } else if (hipmr_c < hipmr_nc) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          { @@STMT@@; }
+        }
+      }
+    }
+  }
+}
+)HIP";
+
 const char* kEwScalar = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head)
@@ -1247,7 +1334,10 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     DType acc = prog.sig.result;
     std::string combine = spec.combine;
     switch (spec.kind) {
-        case KernelKind::EwVector: tmpl = kEwVector; tag = "ew"; break;
+        case KernelKind::EwVector:
+            tmpl = prog.info.shifts.empty() ? kEwVector : kEwVectorShift;
+            tag = "ew";
+            break;
         case KernelKind::EwScalar: tmpl = kEwScalar; tag = "ews"; break;
         case KernelKind::RedS1Vector: tmpl = kRedS1Vector; tag = "rs1"; reduce = true; break;
         case KernelKind::RedS1Scalar: tmpl = kRedS1Scalar; tag = "rs1s"; reduce = true; break;
@@ -1309,8 +1399,32 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             stores += "hipmr_store<HIPMR_NTS>(" + a.name + " + hipmr_off, hipmr_p_" + a.name + "[hipmr_u]); ";
     }
 
+    // shifted reads (vector elementwise kernels): distances, packs and loads
+    std::string shift_init, shift_packs, shift_loads;
+    const bool shifts = spec.kind == KernelKind::EwVector && !prog.info.shifts.empty();
+    if (shifts) {
+        std::string bounds = "long long hipmr_smin = 0, hipmr_smax = 0; ";
+        for (size_t r = 0; r < prog.info.shifts.size(); ++r) {
+            const ShiftRead& sr = prog.info.shifts[r];
+            const ArgDecl& a = prog.sig.args[sr.arg];
+            const std::string k = std::to_string(r);
+            shift_init += "const long long hipmr_s" + k + " = (long long)" + sr.offset + "; ";
+            bounds += "hipmr_smin = hipmr_s" + k + " < hipmr_smin ? hipmr_s" + k + " : hipmr_smin; ";
+            bounds += "hipmr_smax = hipmr_s" + k + " > hipmr_smax ? hipmr_s" + k + " : hipmr_smax; ";
+            shift_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", HIPMR_V> hipmr_q" + k +
+                           "[HIPMR_U]; ";
+            shift_loads += "hipmr_loadu(hipmr_q" + k + "[hipmr_u], " + a.name + " + hipmr_off + hipmr_s" + k + "); ";
+        }
+        shift_init += bounds;
+    }
+    replace_all(body, "@@SHIFT_INIT@@", shift_init);
+    replace_all(body, "@@SHIFT_PACKS@@", shift_packs);
+    replace_all(body, "@@SHIFT_LOADS@@", shift_loads);
+
     std::string scalar_text = join_tokens(prog.toks);
-    std::string vector_text = scan_scalar ? scalar_text : vectorize_accesses(prog.toks, prog.sig);
+    std::string vector_text = scan_scalar ? scalar_text
+                                          : vectorize_accesses(prog.toks, prog.sig,
+                                                               shifts ? prog.info.shifts : std::vector<ShiftRead>{});
     if (scan_scalar) {
         decl_packs.clear();
         loads.clear();

@@ -46,6 +46,7 @@ struct ArgDecl {
     bool write_only = false;  // written unconditionally before any read: no load needed
     bool lane = false;        // accessed as name[i]
     bool uniform = false;     // read as name[<integer literal>] (the same element for every i)
+    bool shifted = false;     // read as name[i + E] / name[i - E], E uniform (see ShiftRead)
 };
 
 // An array the vector kernels move in 16-byte chunks (accessed as name[i] or
@@ -69,9 +70,20 @@ struct Token {
 
 hipmr_status lex(const std::string& src, std::vector<Token>* out);
 
+// A read of an array at a fixed distance from the formal index, name[i + E]
+// or name[i - E], in an elementwise statement: E holds only literals, scalar
+// arguments, n, + - * / % and parentheses, so the distance is the same for
+// every i and the vector kernel loads such reads as (unaligned) chunks.
+struct ShiftRead {
+    size_t arg;                 // index of the array in the signature
+    std::string offset;         // C expression of the signed distance, "(0 + E)" / "(0 - E)"
+};
+
 struct ExprInfo {
-    bool vectorizable = true;   // every array reference is name[i] or a read of a fixed element
+    bool vectorizable = true;   // every array reference is name[i], a read of a fixed element
+                                // or (elementwise) a shifted read of a read-only array
     bool has_writes = false;
+    std::vector<ShiftRead> shifts;   // distinct shifted reads, in order of appearance
 };
 
 // Classifies an elementwise statement list or a map expression against the
@@ -84,7 +96,8 @@ std::string join_tokens(const std::vector<Token>& toks);
 
 // Rewrites every array access name[i] into the register form used by the
 // vector kernels: <name>_p[hipmr_u].v[hipmr_j].
-std::string vectorize_accesses(const std::vector<Token>& toks, const Signature& sig);
+std::string vectorize_accesses(const std::vector<Token>& toks, const Signature& sig,
+                               const std::vector<ShiftRead>& shifts = {});
 
 // Canonical combine operations (see hipmr_reduce).
 enum class Combine { Sum, Max, Min, Generic };

@@ -265,6 +265,49 @@ bool is_assign_op(const Token& t) {
     return t.kind == Token::Punct && ops.count(t.text);
 }
 
+// name[i + E] / name[i - E] at toks[k]: E is built from literals, scalar
+// arguments, n, + - * / % and parentheses (shifts and other operators only
+// inside parentheses, so that i + (E) groups as written).  On a match,
+// *close is the index of the closing ']' and *offset the signed distance.
+bool match_shift(const std::vector<Token>& toks, size_t k, const Signature& sig, size_t* close,
+                 std::string* offset) {
+    if (!(k + 4 < toks.size() && is_punct(toks[k + 1], "[") && toks[k + 2].kind == Token::Ident &&
+          toks[k + 2].text == "i" && (is_punct(toks[k + 3], "+") || is_punct(toks[k + 3], "-"))))
+        return false;
+    static const std::set<std::string> top = {"+", "-", "*", "/", "%", "(", ")"};
+    static const std::set<std::string> nested = {"+", "-", "*", "/", "%", "(", ")", "<<", ">>", "&", "|", "^", "~"};
+    int paren = 0;
+    std::string text = "(0";
+    bool operand = false;
+    for (size_t j = k + 3; j < toks.size(); ++j) {
+        const Token& t = toks[j];
+        if (is_punct(t, "]") && paren == 0) {
+            if (!operand) return false;
+            *close = j;
+            *offset = text + ")";
+            return true;
+        }
+        if (t.kind == Token::Number) {
+            operand = true;
+        } else if (t.kind == Token::Ident) {
+            bool scalar = t.text == "n";
+            for (const ArgDecl& a : sig.args)
+                if (a.name == t.text && !a.pointer) scalar = true;
+            if (!scalar) return false;
+            operand = true;
+        } else if (t.kind == Token::Punct) {
+            if (!(paren == 0 ? top : nested).count(t.text)) return false;
+            if (t.text == "(") ++paren;
+            if (t.text == ")" && --paren < 0) return false;
+            operand = t.text == ")";
+        } else {
+            return false;
+        }
+        text += " " + t.text;
+    }
+    return false;
+}
+
 }  // namespace
 
 hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_map, ExprInfo* out) {
@@ -272,7 +315,7 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
     std::map<std::string, size_t> arg_index;
     for (size_t a = 0; a < sig->args.size(); ++a) {
         sig->args[a].read = sig->args[a].written = sig->args[a].write_only = false;
-        sig->args[a].lane = sig->args[a].uniform = false;
+        sig->args[a].lane = sig->args[a].uniform = sig->args[a].shifted = false;
         arg_index[sig->args[a].name] = a;
     }
     // balance of brackets; forbidden constructs
@@ -330,6 +373,10 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         // a read of one fixed element (name[3]): uniform across i, read directly
         bool constant_index = !lane_local && k + 3 < toks.size() && is_punct(toks[k + 1], "[") &&
                               toks[k + 2].kind == Token::Number && is_punct(toks[k + 3], "]");
+        // a read at a uniform distance from i (elementwise statements only)
+        size_t close = 0;
+        std::string offset;
+        bool shifted = !is_map && !lane_local && !constant_index && match_shift(toks, k, *sig, &close, &offset);
         size_t after;   // token after the closing ']'
         if (lane_local) {
             after = k + 4;
@@ -337,6 +384,12 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         } else if (constant_index) {
             after = k + 4;
             a.uniform = true;
+        } else if (shifted) {
+            after = close + 1;
+            a.shifted = true;
+            bool known = false;
+            for (const ShiftRead& r : out->shifts) known |= r.arg == it->second && r.offset == offset;
+            if (!known) out->shifts.push_back(ShiftRead{it->second, offset});
         } else {
             out->vectorizable = false;
             if (!(k + 1 < toks.size() && is_punct(toks[k + 1], "["))) {
@@ -375,19 +428,36 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         // a fixed element of an array the expression also writes could be
         // written by another i: keep such expressions on the one-element path
         if (d.uniform && d.written) out->vectorizable = false;
+        // so could a shifted element
+        if (d.shifted && d.written) out->vectorizable = false;
     }
+    if (!out->vectorizable) out->shifts.clear();
     if (is_map && out->has_writes)
         return fail(HIPMR_E_UNSUPPORTED, "expression: a map expression may not assign to arrays");
     return HIPMR_OK;
 }
 
-std::string vectorize_accesses(const std::vector<Token>& toks, const Signature& sig) {
+std::string vectorize_accesses(const std::vector<Token>& toks, const Signature& sig,
+                               const std::vector<ShiftRead>& shifts) {
     std::set<std::string> arrays;
     for (auto& a : sig.args)
         if (a.pointer) arrays.insert(a.name);
     std::string s;
     for (size_t k = 0; k < toks.size() && toks[k].kind != Token::End; ++k) {
         const Token& t = toks[k];
+        size_t close = 0;
+        std::string offset;
+        if (!shifts.empty() && t.kind == Token::Ident && arrays.count(t.text) &&
+            !(k > 0 && (is_punct(toks[k - 1], ".") || is_punct(toks[k - 1], "->"))) &&
+            match_shift(toks, k, sig, &close, &offset)) {
+            for (size_t r = 0; r < shifts.size(); ++r)
+                if (sig.args[shifts[r].arg].name == t.text && shifts[r].offset == offset) {
+                    s += " hipmr_q" + std::to_string(r) + "[hipmr_u].v[hipmr_j]";
+                    k = close;
+                    break;
+                }
+            if (k == close) continue;
+        }
         if (t.kind == Token::Ident && arrays.count(t.text) && k + 3 < toks.size() &&
             is_punct(toks[k + 1], "[") && toks[k + 2].kind == Token::Ident && toks[k + 2].text == "i" &&
             is_punct(toks[k + 3], "]") &&

@@ -50,7 +50,7 @@ def test_classifier_read_write_sets():
     assert k.vectorizable
     src = k.source(0)
     assert "hipmr_load<HIPMR_NTL>(hipmr_p_z" in src          # conditional write: z is loaded first
-    k = hm.compile("z[i] = x[i + 1]", "float *z, const float *x")
+    k = hm.compile("z[i] = x[i * 2]", "float *z, const float *x")
     assert not k.vectorizable
     k = hm.compile("q[i] = x[i]", "fp8_e4m3 *q, const bfloat16 *x")
     assert k.vec == 16                                 # 16 bytes of the narrowest array
@@ -72,6 +72,40 @@ def test_fixed_element_reads_stay_on_the_vector_path():
     assert not k.vectorizable
     k = hm.compile("z[i] = x[n - 1]", "float *z, const float *x")
     assert not k.vectorizable
+
+
+def test_shifted_reads_classification():
+    # name[i + E] / name[i - E] with E uniform (literals, scalar arguments, n)
+    # reads an array at the same distance for every i: elementwise statements
+    # keep the vector kernel, with one unaligned chunk load per distinct read
+    sig = "float *q, const float *p, int nx"
+    stmt = ("int c = i % nx; q[i] = 4.0f*p[i] - (c != 0 ? p[i-1] : 0.0f) - (c != nx - 1 ? p[i+1] : 0.0f)"
+            " - (i >= nx ? p[i-nx] : 0.0f) - (i + nx < n ? p[i+nx] : 0.0f)")
+    k = hm.compile(stmt, sig)
+    assert k.vectorizable and k.vec == 4
+    src = k.source(0)
+    for r, off in enumerate(("(0 - 1)", "(0 + 1)", "(0 - nx)", "(0 + nx)")):
+        assert f"hipmr_s{r} = (long long){off}" in src
+        assert f"hipmr_loadu(hipmr_q{r}[hipmr_u], p + hipmr_off + hipmr_s{r})" in src
+    assert "hipmr_q4" not in src                       # four distinct distances
+    assert "hipmr_load<HIPMR_NTL>(hipmr_p_p" in src    # p[i] itself: an aligned chunk
+    # a repeated read shares its load; bfloat16 narrows VEC to 8
+    k = hm.compile("o[i] = x[i + 2*k] + x[i + 2*k] * x[i - (k)]", "float *o, const bfloat16 *x, long k")
+    assert k.vectorizable and k.vec == 8
+    assert "hipmr_q1" in k.source(0) and "hipmr_q2" not in k.source(0)
+    # no shifted reads: the source of a plain kernel does not change
+    plain = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y")
+    assert "hipmr_loadu" not in plain.source(0)
+    # cases that keep the one-element kernel
+    for stmt, sig in (("x[i] = x[i + 1]", "float *x"),                        # shifted array written
+                      ("int c = 1; z[i] = x[i + c]", "float *z, const float *x"),   # local in E
+                      ("z[i] = x[i + nx << 1]", "float *z, const float *x, int nx"),  # (i + nx) << 1
+                      ("z[i] = x[i + y[0]]", "float *z, const float *x, const int *y"),  # array in E
+                      ("z[i] = x[i + i]", "float *z, const float *x")):
+        assert not hm.compile(stmt, sig).vectorizable, stmt
+    assert hm.compile("z[i] = x[i + (nx << 1)]", "float *z, const float *x, int nx").vectorizable
+    # map-reduce maps keep the one-element kernels for shifted reads
+    assert not hm.compile("x[i + 1] - x[i]", "float: const float *x").vectorizable
 
 
 def test_generated_source_shape():

@@ -396,3 +396,61 @@ def test_fixed_element_reads_vector_path(dev, offset):
     out = reduce_on_gpu(r, "a+b", "0", n, [x0d[offset:offset + n], dev_array(s)])
     assert_reduce(out, oracle.reduce("float: const float *x, const float *s", "s[1] * x[i]", "a+b", "0",
                                      n, [x[offset:offset + n], s]), "fixed-element reduce")
+
+
+# ---------------------------------------------------------------- shifted reads
+SHIFT_CASES = [
+    ("z[i] = (i >= 1 ? x[i - 1] : 0.0f) + 2.0f * x[i] + (i + 1 < n ? x[i + 1] : 0.0f)",
+     "float *z, const float *x", "float32", ()),
+    ("z[i] = (i + k < n && i + k >= 0 ? x[i + k] : 1.5f) * 0.5f - x[i]",
+     "float *z, const float *x, long k", "float32", (np.int64(1000),)),
+    ("z[i] = (i + k < n && i + k >= 0 ? x[i + k] : 1.5f) * 0.5f - x[i]",
+     "float *z, const float *x, long k", "float32", (np.int64(-37),)),
+    ("z[i] = (i + k < n && i + k >= 0 ? x[i + k] : 1.5f) * 0.5f - x[i]",
+     "float *z, const float *x, long k", "float32", (np.int64(10 ** 6),)),   # beyond n: all per element
+    ("o[i] = (i + 2*m < n ? (float)b[i + 2*m] : 0.0f) + (i >= (m) ? (float)b[i - (m)] : 0.0f)",
+     "bfloat16 *o, const bfloat16 *b, int m", "bfloat16", (np.int32(5),)),
+    ("w[i] = (i + 3 < n ? v[i + 3] : 0) - (i >= 2 ? v[i - 2] : 0)", "int *w, const int *v", "int32", ()),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SHIFT_CASES)))
+@pytest.mark.parametrize("n,offset", [(70001, 0), (70001, 3), (5, 1), (4099, 2)])
+def test_shifted_reads_vector_path(dev, case, n, offset):
+    """name[i + E] reads (E uniform) run on the vector kernel: unaligned chunk
+    loads, per-element evaluation within the largest distance of either end.
+    Results match the oracle and, bit for bit, the one-element kernel."""
+    stmt, sig, dt, scalars = SHIFT_CASES[case]
+    rng = np.random.default_rng(300 + case + n + offset)
+    if dt == "int32":
+        src = rng.integers(-10 ** 6, 10 ** 6, n + 8).astype(np.int32)
+        out_np, tdt = np.int32, torch.int32
+    else:
+        src = rng.uniform(-2, 2, n + 8).astype(np.float32)
+        out_np, tdt = np.float32, torch.float32
+    if dt == "bfloat16":
+        bits = torch.from_numpy(src).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+        sd = dev_array(bits, "bfloat16")
+        host_in = bits[offset:offset + n]
+        tdt = torch.bfloat16
+        zero = np.zeros(n, np.uint16)
+    else:
+        sd = dev_array(src)
+        host_in = src[offset:offset + n]
+        zero = np.zeros(n, out_np)
+    k = hm.compile(stmt, sig, name="shift_t")
+    assert k.vectorizable
+    outs = []
+    for cfg in (None, {"flags": hm.CFG_FORCE_SCALAR}):
+        buf = torch.zeros(n + 8, dtype=tdt, device=dev)
+        z = buf[offset:offset + n]
+        hm.elementwise(k, n, [z, sd[offset:offset + n], *[int(v) for v in scalars]], config=cfg)
+        torch.cuda.synchronize()
+        assert k.last_symbols()[0].split("_")[-2] == ("ew" if cfg is None else "ews")
+        tail = host_bits(buf[offset + n:])
+        assert np.all(tail == 0), "wrote past the end"
+        outs.append(host_bits(z))
+    assert np.array_equal(outs[0], outs[1]), "vector and one-element kernels differ"
+    ref = oracle.elementwise(sig, stmt, n, [zero, host_in, *scalars])
+    name = sig.split("*")[1].split(",")[0].strip()
+    assert_lanes(z, ref[name], dt, what=f"{stmt} n={n} offset={offset} {scalars}")
