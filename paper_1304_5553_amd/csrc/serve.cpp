@@ -638,12 +638,12 @@ struct hipmr_server {
         // one-launch-pair-per-job loop would (packing a short queue into one
         // stream measured a longer p99 than spreading it); a longer queue is
         // spread over the free slots, ceil(waiting / free) jobs per batch, so
-        // batches grow with the backlog and drain it.  A job of more than solo_bytes runs
-        // in a batch of its own; a batch of smaller jobs is packed past such
-        // jobs, which keep their places for the next free slot, so a small
-        // job never waits for a large one's tiles.  Admission keeps arrival
-        // order: packing stops at the first job, skipped or not, that does not
-        // fit the budget.
+        // batches grow with the backlog and drain it.  A job of more than
+        // solo_bytes runs in a batch of its own; a batch of smaller jobs is
+        // packed past such jobs, which stay queued (not yet admitted) for the
+        // next free slot, so a small job never waits for a large one's tiles.
+        // Packing stops at the first job, skipped or not, that does not fit
+        // the budget: no job is admitted while an earlier one does not fit.
         int free_slots = 0;
         for (const Slot& s : slots) free_slots += !s.busy;
         for (Slot& s : slots) {
