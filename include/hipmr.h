@@ -409,8 +409,9 @@ typedef struct hipmr_server *hipmr_server_t;
 size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
 
 /* Serving extension of the map-reduce: starts a request loop on a host thread
- * for the current device.  The loop releases arrivals, admits them in arrival
- * order while the bytes of admitted, unfinished jobs stay within the budget,
+ * for the current device.  The loop releases arrivals, admits them while the
+ * bytes of admitted, unfinished jobs stay within the budget (no job is
+ * admitted while an earlier one does not fit; small jobs may pass a large one),
  * spreads admitted jobs over the free streams, one batch per stream (continuous
  * batching: jobs that arrive while others run join the next batch on a free
  * stream; one job per free stream while at most batch_backlog jobs per free
