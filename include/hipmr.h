@@ -186,7 +186,12 @@ size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n);
  *               bytes (E_WORKSPACE otherwise); it is scratch for block partials.
  * Two launches on stream (block partials, then one block folding them), no
  * atomics; for a given device, n and launch configuration the result is
- * bitwise reproducible.  n == 0 writes neutral.
+ * bitwise reproducible.  n == 0 writes neutral.  The map reads arrays in
+ * chunks as described for hipmr_elementwise, shifted reads name[i +/- E]
+ * included (every lane loads every chunk, clamped into [0, n), and chunks
+ * near the ends are mapped one element at a time); the other map-reduce
+ * entry points read shifted elements one at a time inside their vector
+ * kernels.
  * Errors: E_INVALID, E_MISMATCH (elementwise handle or map_expr), E_PARSE,
  * E_COMPILE, E_WORKSPACE, E_HIP. */
 hipmr_status hipmr_reduce(hipmr_handle h, const char *map_expr, const char *combine_op,

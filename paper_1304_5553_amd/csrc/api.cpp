@@ -646,6 +646,7 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
         {"x[i]", "double: const fp8_e4m3 *x", "min", "INFINITY"},
         {"k[i]", "unsigned: const unsigned *k", "a|b", "0u"},
         {"x[n - 1 - i]", "float: const float *x", "a+b", "0"},
+        {"(i + 1 < n ? x[i + 1] : 0.0f) * x[i]", "float: const float *x", "a+b", "0"},
         {"x[i]", "float: const fp8_e4m3 *x", "a+b", "0"},
         {"x[i]", "float: const bfloat16 *x", "a+b", "0"},
         {"x[i] * y[i]", "float: const half *x, const half *y", "a+b", "0"},

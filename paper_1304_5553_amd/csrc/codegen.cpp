@@ -342,7 +342,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 // V elements from name + off + E.  A chunk whose shifted loads would leave
 // [0, n) (within |E| of either end) runs the statement one element at a time
 // instead, with the statement's own guards.
-const char* kEwVectorShift = R"HIP(
+const char* kShiftHelpers = R"HIP(
 // 16 bytes at 4-byte alignment: one dwordx4 load (the memory system accepts
 // dword-aligned multi-dword accesses); narrower element types go by memcpy
 typedef unsigned int hipmr_u32x4u __attribute__((ext_vector_type(4), aligned(4)));
@@ -359,6 +359,21 @@ __device__ __forceinline__ void hipmr_loadu(hipmr_pack<T, N>& p, const T* src) {
   }
 }
 
+// XCD-aware order: workgroups go round-robin to the 8 XCDs, each with its own
+// L2.  Renumbered, each XCD takes a contiguous run of chunks, so the
+// neighbouring elements a shifted read reaches were loaded by the same XCD.
+// a V-element window start clamped into [0, hi] (hi = n - V >= 0)
+__device__ __forceinline__ long long hipmr_clampv(long long o, long long hi) {
+  return o < 0 ? 0 : (o > hi ? hi : o);
+}
+
+__device__ __forceinline__ unsigned hipmr_xcd_block() {
+  const unsigned x = blockIdx.x % 8u, q = gridDim.x / 8u, r = gridDim.x % 8u;
+  return x * q + (x < r ? x : r) + blockIdx.x / 8u;
+}
+)HIP";
+
+const char* kEwVectorShift = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head)
 {
@@ -380,14 +395,9 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
       { @@STMT@@; }
     }
   }
-  // XCD-aware order: workgroups go round-robin to the 8 XCDs, each with its
-  // own L2.  Renumbered, each XCD takes a contiguous run of chunks, so the
-  // neighbouring elements a shifted read reaches were loaded by the same XCD.
-  const unsigned hipmr_x = blockIdx.x % 8u, hipmr_q8 = gridDim.x / 8u, hipmr_r8 = gridDim.x % 8u;
-  const unsigned hipmr_bid = hipmr_x * hipmr_q8 + (hipmr_x < hipmr_r8 ? hipmr_x : hipmr_r8) + blockIdx.x / 8u;
   const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
-  for (long long hipmr_c0 = (long long)hipmr_bid * (HIPMR_B * HIPMR_U) + threadIdx.x; hipmr_c0 < hipmr_nc;
-       hipmr_c0 += hipmr_step) {
+  for (long long hipmr_c0 = (long long)hipmr_xcd_block() * (HIPMR_B * HIPMR_U) + threadIdx.x;
+       hipmr_c0 < hipmr_nc; hipmr_c0 += hipmr_step) {
     @@DECL_PACKS@@
     @@SHIFT_PACKS@@
     bool hipmr_vec[HIPMR_U];
@@ -531,6 +541,81 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
     hipmr_r = hipmr_combine(hipmr_r, (hipmr_acc)(@@MAP@@));
   }
   hipmr_r = hipmr_block_reduce<@@BLOCK@@>(hipmr_r, hipmr_neutral);
+  if (threadIdx.x == 0) hipmr_partial[blockIdx.x] = hipmr_r;
+}
+)HIP";
+
+// Reduce stage 1 for maps with shifted reads: as kEwVectorShift, each
+// distinct shifted read is one unaligned chunk load, chunks within the largest
+// distance of either end are mapped one element at a time, and workgroups
+// take XCD-contiguous runs of chunks.  Each lane folds its chunks in order
+// into U accumulators; the partial of workgroup b lands in partial[b].
+const char* kRedS1VectorShift = R"HIP(
+extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
+@@KNAME@@(@@PARAMS@@, long long hipmr_n, long long hipmr_head,
+          hipmr_acc* __restrict__ hipmr_partial)
+{
+  typedef @@IDX@@ hipmr_idx;
+  constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@;
+  constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
+  const hipmr_idx n = (hipmr_idx)hipmr_n;
+  @@SHIFT_INIT@@
+  const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
+  hipmr_acc hipmr_a[HIPMR_U];
+#pragma unroll
+  for (int u = 0; u < HIPMR_U; ++u) hipmr_a[u] = hipmr_neutral;
+  const long long hipmr_h = hipmr_head < hipmr_n ? hipmr_head : hipmr_n;
+  const long long hipmr_nc = (hipmr_n - hipmr_h) / HIPMR_V;
+  const long long hipmr_t0 = hipmr_h + hipmr_nc * HIPMR_V;
+  if (blockIdx.x == 0) {
+    if ((long long)threadIdx.x < hipmr_h) {
+      const hipmr_idx i = (hipmr_idx)threadIdx.x;
+      hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
+    }
+    if ((long long)threadIdx.x < hipmr_n - hipmr_t0) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_t0 + threadIdx.x);
+      hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
+    }
+  }
+  const long long hipmr_step = (long long)gridDim.x * (HIPMR_B * HIPMR_U);
+  for (long long hipmr_c0 = (long long)hipmr_xcd_block() * (HIPMR_B * HIPMR_U) + threadIdx.x;
+       hipmr_c0 < hipmr_nc; hipmr_c0 += hipmr_step) {
+    @@DECL_PACKS@@
+    @@SHIFT_PACKS@@
+    bool hipmr_vec[HIPMR_U];
+    // every lane loads every chunk, from a clamped in-range window where its
+    // chunk is past the end or within a shifted read's distance of an end
+    // (those chunks are then evaluated element by element): no branch
+    // separates the loads, so they all stay in flight together
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
+      const long long hipmr_off = hipmr_c < hipmr_nc ? hipmr_h + hipmr_c * HIPMR_V : hipmr_h;
+      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_off + hipmr_smin >= 0 &&
+                           hipmr_off + HIPMR_V + hipmr_smax <= hipmr_n;
+      @@LOADS@@
+      @@SHIFT_LOADS@@
+    }
+#pragma unroll
+    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+      const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
+      const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
+      if (hipmr_vec[hipmr_u]) {
+#pragma unroll
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@VMAP@@));
+        }
+      } else if (hipmr_c < hipmr_nc) {
+        for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
+          const hipmr_idx i = (hipmr_idx)(hipmr_off + hipmr_j);
+          hipmr_a[hipmr_u] = hipmr_combine(hipmr_a[hipmr_u], (hipmr_acc)(@@MAP@@));
+        }
+      }
+    }
+  }
+  hipmr_acc hipmr_r = hipmr_fold<HIPMR_U>(hipmr_a);
+  hipmr_r = hipmr_block_reduce<HIPMR_B>(hipmr_r, hipmr_neutral);
   if (threadIdx.x == 0) hipmr_partial[blockIdx.x] = hipmr_r;
 }
 )HIP";
@@ -1339,7 +1424,11 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             tag = "ew";
             break;
         case KernelKind::EwScalar: tmpl = kEwScalar; tag = "ews"; break;
-        case KernelKind::RedS1Vector: tmpl = kRedS1Vector; tag = "rs1"; reduce = true; break;
+        case KernelKind::RedS1Vector:
+            tmpl = prog.info.shifts.empty() ? kRedS1Vector : kRedS1VectorShift;
+            tag = "rs1";
+            reduce = true;
+            break;
         case KernelKind::RedS1Scalar: tmpl = kRedS1Scalar; tag = "rs1s"; reduce = true; break;
         case KernelKind::RedS2: tmpl = kRedS2; tag = "rs2"; reduce = true; break;
         case KernelKind::CompS1Vector:
@@ -1401,7 +1490,9 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
 
     // shifted reads (vector elementwise kernels): distances, packs and loads
     std::string shift_init, shift_packs, shift_loads;
-    const bool shifts = spec.kind == KernelKind::EwVector && !prog.info.shifts.empty();
+    // (the other vector kernels read shifted elements directly, as written)
+    const bool shifts = (spec.kind == KernelKind::EwVector || spec.kind == KernelKind::RedS1Vector) &&
+                        !prog.info.shifts.empty();
     if (shifts) {
         std::string bounds = "long long hipmr_smin = 0, hipmr_smax = 0; ";
         for (size_t r = 0; r < prog.info.shifts.size(); ++r) {
@@ -1413,7 +1504,12 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             bounds += "hipmr_smax = hipmr_s" + k + " > hipmr_smax ? hipmr_s" + k + " : hipmr_smax; ";
             shift_packs += std::string("hipmr_pack<") + dtype_device_name(a.dtype) + ", HIPMR_V> hipmr_q" + k +
                            "[HIPMR_U]; ";
-            shift_loads += "hipmr_loadu(hipmr_q" + k + "[hipmr_u], " + a.name + " + hipmr_off + hipmr_s" + k + "); ";
+            // the reduce kernel loads every chunk (clamped into the array);
+            // the elementwise kernel loads only chunks it evaluates as vectors
+            const std::string at = spec.kind == KernelKind::RedS1Vector
+                                       ? "hipmr_clampv(hipmr_off + hipmr_s" + k + ", hipmr_n - HIPMR_V)"
+                                       : "hipmr_off + hipmr_s" + k;
+            shift_loads += "hipmr_loadu(hipmr_q" + k + "[hipmr_u], " + a.name + " + " + at + "); ";
         }
         shift_init += bounds;
     }
@@ -1476,6 +1572,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     if (comp) src << kCompHelpers;
     if (seg) src << kSegHelpers;
     if (scan) src << kScanHelpers;
+    if (shifts) src << kShiftHelpers;
     // the symbol carries a hash of the whole source (prelude and helpers
     // included), so any change to the generated code renames the kernel
     src << body;

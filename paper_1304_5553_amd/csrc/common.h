@@ -71,9 +71,10 @@ struct Token {
 hipmr_status lex(const std::string& src, std::vector<Token>* out);
 
 // A read of an array at a fixed distance from the formal index, name[i + E]
-// or name[i - E], in an elementwise statement: E holds only literals, scalar
-// arguments, n, + - * / % and parentheses, so the distance is the same for
-// every i and the vector kernel loads such reads as (unaligned) chunks.
+// or name[i - E]: E holds only literals, scalar arguments, n, + - * / % and
+// parentheses, so the distance is the same for every i.  The vector
+// elementwise and plain reduce kernels load such reads as (unaligned) chunks;
+// the other vector kernels read them element by element, as written.
 struct ShiftRead {
     size_t arg;                 // index of the array in the signature
     std::string offset;         // C expression of the signed distance, "(0 + E)" / "(0 - E)"
@@ -81,7 +82,7 @@ struct ShiftRead {
 
 struct ExprInfo {
     bool vectorizable = true;   // every array reference is name[i], a read of a fixed element
-                                // or (elementwise) a shifted read of a read-only array
+                                // or a shifted read of an array the expression does not write
     bool has_writes = false;
     std::vector<ShiftRead> shifts;   // distinct shifted reads, in order of appearance
 };

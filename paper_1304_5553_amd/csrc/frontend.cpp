@@ -373,10 +373,10 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
         // a read of one fixed element (name[3]): uniform across i, read directly
         bool constant_index = !lane_local && k + 3 < toks.size() && is_punct(toks[k + 1], "[") &&
                               toks[k + 2].kind == Token::Number && is_punct(toks[k + 3], "]");
-        // a read at a uniform distance from i (elementwise statements only)
+        // a read at a uniform distance from i
         size_t close = 0;
         std::string offset;
-        bool shifted = !is_map && !lane_local && !constant_index && match_shift(toks, k, *sig, &close, &offset);
+        bool shifted = !lane_local && !constant_index && match_shift(toks, k, *sig, &close, &offset);
         size_t after;   // token after the closing ']'
         if (lane_local) {
             after = k + 4;

@@ -104,8 +104,11 @@ def test_shifted_reads_classification():
                       ("z[i] = x[i + i]", "float *z, const float *x")):
         assert not hm.compile(stmt, sig).vectorizable, stmt
     assert hm.compile("z[i] = x[i + (nx << 1)]", "float *z, const float *x, int nx").vectorizable
-    # map-reduce maps keep the one-element kernels for shifted reads
-    assert not hm.compile("x[i + 1] - x[i]", "float: const float *x").vectorizable
+    # maps: the plain reduce loads shifted reads as chunks too
+    r = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f) - x[i]", "float: const float *x")
+    assert r.vectorizable
+    assert ("hipmr_loadu(hipmr_q0[hipmr_u], x + hipmr_clampv(hipmr_off + hipmr_s0, hipmr_n - HIPMR_V))"
+            in r.source(2, "a+b", "0"))
 
 
 def test_generated_source_shape():

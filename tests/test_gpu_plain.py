@@ -454,3 +454,55 @@ def test_shifted_reads_vector_path(dev, case, n, offset):
     ref = oracle.elementwise(sig, stmt, n, [zero, host_in, *scalars])
     name = sig.split("*")[1].split(",")[0].strip()
     assert_lanes(z, ref[name], dt, what=f"{stmt} n={n} offset={offset} {scalars}")
+
+
+@pytest.mark.parametrize("offset", [0, 1])
+def test_shifted_maps(dev, offset):
+    """Maps with shifted reads: the plain reduce loads them as chunks (rs1),
+    the other facilities read them element by element inside their vector
+    kernels; every result matches the oracle."""
+    n = 300007
+    rng = np.random.default_rng(400 + offset)
+    x = rng.uniform(-1, 1, n + 8).astype(np.float32)
+    k = rng.integers(-1000, 1000, n + 8).astype(np.int32)
+    xs, ks = x[offset:offset + n], k[offset:offset + n]
+    xd, kd = dev_array(x)[offset:offset + n], dev_array(k)[offset:offset + n]
+    # float sum of a lag-1 product: vector (shifted chunks) and one-element kernels
+    sig, mp = "float: const float *x", "(i + 1 < n ? x[i + 1] : 0.0f) * x[i]"
+    h = hm.compile(mp, sig, name="lag1")
+    assert h.vectorizable
+    ref = oracle.reduce(sig, mp, "a+b", "0", n, [xs])
+    for cfg, tag in ((None, "rs1"), ({"flags": hm.CFG_FORCE_SCALAR}, "rs1s")):
+        out = reduce_on_gpu(h, "a+b", "0", n, [xd], config=cfg)
+        assert h.last_symbols()[0].split("_")[-2] == tag
+        assert_reduce(out, ref, f"lag-1 sum {tag}")
+    # exact integer sums at positive and negative distances, and a shifted max
+    isig, imp = "long: const int *k, int s", "(i + s < n && i + s >= 0 ? k[i + s] : 0) - k[i]"
+    hi = hm.compile(imp, isig, name="lagk")
+    for s in (4097, -3, 1 << 20):
+        out = reduce_on_gpu(hi, "a+b", "0", n, [kd, s])
+        assert_reduce(out, oracle.reduce(isig, imp, "a+b", "0", n, [ks, np.int32(s)]), f"int lag {s}")
+    msig, mmp = "float: const float *x, long d", "i >= d ? x[i - d] : -INFINITY"
+    hmx = hm.compile(mmp, msig, name="lagmax")
+    out = reduce_on_gpu(hmx, "max(a,b)", "-INFINITY", n, [xd, 5])
+    assert_reduce(out, oracle.reduce(msig, mmp, "max(a,b)", "-INFINITY", n, [xs, np.int64(5)]), "shifted max")
+    # compensated sum (FP64 result) with the shifted map
+    hc = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f)", "float: const float *x", name="lagc")
+    g = hm.reduce_compensated(hc, n, [xd]).item()
+    want = oracle.exact_sum(xs[1:].astype(np.float64))
+    assert abs(g - want) <= 1e-6 * float(np.abs(xs).sum()), (g, want)
+    # segmented integer sums: the map reads across segment boundaries (i is global)
+    cuts = np.sort(rng.integers(0, n, 499))
+    offs = np.concatenate([[0], cuts, [n]]).astype(np.int64)
+    sseg = torch.empty(len(offs) - 1, dtype=torch.int64, device=dev)
+    hm.reduce_segmented(hi, "a+b", "0", dev_array(offs), n, [kd, 7], sseg)
+    torch.cuda.synchronize()
+    mv = oracle.map_values(isig, imp, n, [ks, np.int32(7)]).v.astype(np.int64)
+    assert host_bits(sseg).tolist() == [int(mv[a:b].sum()) for a, b in zip(offs[:-1], offs[1:])]
+    # inclusive scan of the shifted map
+    ssig, smp = "long: const int *k", "i >= 1 ? k[i - 1] : 0"
+    hs = hm.compile(smp, ssig, name="lagscan")
+    sc = torch.empty(n, dtype=torch.int64, device=dev)
+    hm.scan(hs, "a+b", "0", n, [kd], sc)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_bits(sc), oracle.scan(ssig, smp, "a+b", "0", n, [ks]).values)
