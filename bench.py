@@ -249,7 +249,7 @@ def bench_cg(torch, hm, dev):
                 row[mode] = {"ms_per_iter": round(ms, 5),
                              "GB/s": round(hcg.BYTES_PER_UNKNOWN * n / ms / 1e6, 1)}
             row["graph_speedup"] = round(row["eager"]["ms_per_iter"] / row["graph"]["ms_per_iter"], 2)
-            row["rr_after_50"] = float(solver.s[0].item())
+            row["rr_after_50"] = float(solver.rr.item())
         res[f"{nx}x{nx}"] = row
         del solver, graph, b
         torch.cuda.empty_cache()

@@ -39,26 +39,19 @@ def test_update_and_scalar_kernels(dev):
     n = 40009
     rng = np.random.default_rng(3)
     x, r, p, q = (rng.uniform(-1, 1, n).astype(np.float32) for _ in range(4))
-    s = np.array([2.0, 3.0, 0.375, 0.5, -0.25, 0, 0, 0], np.float32)
-    xd, rd, pd, qd, sd = (dev_array(a) for a in (x, r, p, q, s))
+    c = np.array([2.0, 3.0], np.float32)          # this iteration's (r . r, p . Ap)
+    d = np.array([0.5, 7.0], np.float32)          # the next r . r (d[1] unused)
+    xd, rd, pd, qd, cd, dd = (dev_array(a) for a in (x, r, p, q, c, d))
     k = hm.compile(hcg.UPDATE[1], hcg.UPDATE[0], name="cg_update_t")
-    assert k.vectorizable
-    hm.elementwise(k, n, [xd, rd, pd, qd, sd])
+    assert k.vectorizable                          # c[0], c[1], d[0] are fixed elements
+    hm.elementwise(k, n, [xd, rd, pd, qd, cd, dd])
     torch.cuda.synchronize()
-    ref = oracle.elementwise(hcg.UPDATE[0], hcg.UPDATE[1], n, [x, r, p, q, s])
+    ref = oracle.elementwise(hcg.UPDATE[0], hcg.UPDATE[1], n, [x, r, p, q, c, d])
     for name, t in (("x", xd), ("r", rd), ("p", pd)):
         assert_lanes(t, ref[name], "float32", what=f"update {name}")
     rn = hm.compile(hcg.RR_NEXT[1], hcg.RR_NEXT[0], name="cg_rrn_t")
-    out = reduce_on_gpu(rn, "a+b", "0", n, [dev_array(r), dev_array(q), sd])
-    assert_reduce(out, oracle.reduce(hcg.RR_NEXT[0], hcg.RR_NEXT[1], "a+b", "0", n, [r, q, s]), "rr next")
-    a = hm.compile(hcg.ALPHA[1], hcg.ALPHA[0], name="cg_alpha_t")
-    b = hm.compile(hcg.BETA[1], hcg.BETA[0], name="cg_beta_t")
-    hm.elementwise(a, 1, [sd[2:3], sd[0:1], sd[1:2]])
-    hm.elementwise(b, 1, [sd[4:5], sd[0:1], sd[3:4]])
-    torch.cuda.synchronize()
-    g = host_bits(sd)
-    assert g[2] == np.float32(2.0) / np.float32(3.0)
-    assert g[4] == np.float32(0.5) / np.float32(2.0) and g[0] == np.float32(0.5)
+    out = reduce_on_gpu(rn, "a+b", "0", n, [dev_array(r), dev_array(q), cd])
+    assert_reduce(out, oracle.reduce(hcg.RR_NEXT[0], hcg.RR_NEXT[1], "a+b", "0", n, [r, q, c]), "rr next")
 
 
 def make_problem(nx, ny, seed):
@@ -76,11 +69,11 @@ def test_cg_converges_and_tracks_the_oracle(dev):
         solver = hcg.PoissonCG(nx, ny, device=dev, stream=stream)
         bd = dev_array(b)
         solver.start(bd)
-        rr_gpu = [host_bits(solver.s)[0]]
+        rr_gpu = [host_bits(solver.rr)[0]]
         for _ in range(12):
             solver.step()
             stream.synchronize()
-            rr_gpu.append(host_bits(solver.s)[0])
+            rr_gpu.append(host_bits(solver.rr)[0])
         _, hist = oracle.cg(b.astype(np.float64), nx, 12)
         rel = np.abs(np.array(rr_gpu, np.float64) / np.array(hist["rr"]) - 1)
         assert rel.max() < 1e-3, rel
@@ -102,6 +95,8 @@ def test_graph_replay_equals_eager(dev):
         solver.solve(bd, 20)
         stream.synchronize()
         x_eager, s_eager = solver.x.clone(), solver.s.clone()
+        with pytest.raises(hm.InvalidError):
+            solver.capture(3)                     # replays must end where they start
         graph = solver.capture(10)
         for rep in range(3):                      # replays after unrelated eager work
             solver.start(bd)
@@ -121,6 +116,6 @@ def test_cg_at_scale_tracks_the_oracle(dev, nx, ny, iters):
         solver = hcg.PoissonCG(nx, ny, device=dev, stream=stream)
         solver.solve(dev_array(b), iters)
         stream.synchronize()
-        rr = float(host_bits(solver.s)[0])
+        rr = float(host_bits(solver.rr)[0])
     _, hist = oracle.cg(b.astype(np.float64), nx, iters)
     assert abs(rr / hist["rr"][-1] - 1) < 1e-2, (rr, hist["rr"][-1])
