@@ -421,7 +421,9 @@ size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
  * batching: jobs that arrive while others run join the next batch on a free
  * stream; one job per free stream while at most batch_backlog jobs per free
  * stream wait, else ceil(waiting / free streams) jobs per batch; a job over
- * solo_bytes runs alone and small jobs are packed past it) and
+ * solo_bytes runs alone and small jobs are packed past it; a job of at most
+ * 16 tiles alone runs in one launch, one block computing and folding its
+ * tiles, unless max_batch_jobs is 1) and
  * launches it as two run-time compiled kernels: a persistent kernel whose
  * waves take tiles of any job (wave-uniform switch over template x dtype) and
  * one block per job folding its tiles in a fixed order.  A job's tiles depend

@@ -50,6 +50,7 @@ constexpr int kFinBlock = 1024;           // final fold: one block per job
 constexpr int kMaxBatchJobs = 4096;      // jobs per batch (their tile offsets are staged in LDS)
 constexpr int kInlineJobs = 24;          // descriptors passed as kernel arguments
 constexpr int kMaxSkipped = 64;          // large jobs one batch of small ones may be packed past
+constexpr int kOneLaunchTiles = 16;      // a job of at most this many tiles alone: one launch
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
@@ -346,6 +347,24 @@ extern "C" __global__ void __launch_bounds__(1024)
   hipmr_job_finish(J, J.tile0, t1, tpart, flags + j, seq);
 }
 
+// A small job in one launch: one block of 1024 threads computes the tile
+// partials (tile t by wave t mod 16, the arithmetic of the tile kernels) and,
+// after a barrier, folds them as the fold kernels do, so the result is
+// bitwise the one of any other path.
+extern "C" __global__ void __launch_bounds__(1024)
+@@PREFIX@@_one(hipmr_sjob J, float2* __restrict__ tpart, unsigned long long* flags,
+               unsigned long long seq)
+{
+  const int lane = threadIdx.x & 63;
+  const int tiles = hipmr_job_geom(J).tiles;
+  for (int t = threadIdx.x >> 6; t < tiles; t += HIPMR_FIN_BLOCK / 64) {
+    const float2 r = hipmr_job_dispatch(J, t, lane);
+    if (lane == 0) tpart[t] = r;
+  }
+  __syncthreads();
+  hipmr_job_finish(J, 0, tiles, tpart, flags, seq);
+}
+
 // One job, descriptor by value: the one-launch-pair-per-job path.
 extern "C" __global__ void __launch_bounds__(256)
 @@PREFIX@@_one1(hipmr_sjob J, float2* __restrict__ tpart)
@@ -459,7 +478,7 @@ struct hipmr_server {
     std::shared_ptr<CodeObject> co;
     hipModule_t module = nullptr;
     hipFunction_t f_s1 = nullptr, f_s2 = nullptr, f_one1 = nullptr, f_one2 = nullptr;
-    hipFunction_t f_i1 = nullptr, f_i2 = nullptr;
+    hipFunction_t f_i1 = nullptr, f_i2 = nullptr, f_one = nullptr;
     std::string prefix;
     int cus = 256;
 
@@ -528,7 +547,16 @@ struct hipmr_server {
     hipmr_status launch_batch(Slot& s) {
         const int nj = (int)s.jobs.size();
         ++s.seq;
-        if (nj == 1) {              // one job: its descriptor by value
+        if (nj == 1 && cfg.max_batch_jobs > 1 && s.jobs[0].tiles <= kOneLaunchTiles) {
+            // a small job alone: one launch (the one-launch-pair-per-job
+            // baseline, max_batch_jobs = 1, keeps its two)
+            const Pending& p = s.jobs[0];
+            DevJob d{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
+                     p.job.out, p.job.a, p.job.b};
+            void* a[4] = {&d, &s.tpart, &s.dev_flags, &s.seq};
+            hipError_t e = hipModuleLaunchKernel(f_one, 1, 1, 1, kFinBlock, 1, 1, 0, s.stream, a, nullptr);
+            if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("serving launch: ") + hipGetErrorString(e));
+        } else if (nj == 1) {       // one job: its descriptor by value
             const Pending& p = s.jobs[0];
             DevJob d{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
                      p.job.out, p.job.a, p.job.b};
@@ -786,7 +814,7 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
     if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
     struct { hipFunction_t* f; const char* suffix; } fns[] = {
         {&s->f_s1, "_s1"}, {&s->f_s2, "_s2"}, {&s->f_one1, "_one1"}, {&s->f_one2, "_one2"},
-        {&s->f_i1, "_i1"}, {&s->f_i2, "_i2"}};
+        {&s->f_i1, "_i1"}, {&s->f_i2, "_i2"}, {&s->f_one, "_one"}};
     for (auto& f : fns) {
         e = hipModuleGetFunction(f.f, s->module, (s->prefix + f.suffix).c_str());
         if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
