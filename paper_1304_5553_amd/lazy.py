@@ -14,6 +14,11 @@ eager array arithmetic, for comparison.
 
 Values are computed in float (the storage formats bfloat16 / half / FP8 are
 read as float); integer leaves are converted to float.
+
+`shift(e, k, fill)` is e at index i + k (fill outside [0, n)): its leaves
+render as shifted reads a[i + k], which the vector kernels load as
+unaligned chunks, so a stencil such as x - 0.5 * (shift(x, -1) + shift(x, 1))
+is one fused kernel too.
 """
 
 from __future__ import annotations
@@ -117,6 +122,14 @@ def _fn(name):
 sqrt, exp, log, sin, cos, abs, maximum, minimum = (_fn(n) for n in _FUNCS)   # noqa: A001
 
 
+def shift(node, k, fill=0.0):
+    """The expression at index i + k (an integer), `fill` where i + k falls
+    outside [0, n)."""
+    if not isinstance(k, numbers.Integral) or isinstance(k, bool):
+        raise TypeError("a shift distance is an integer")
+    return LazyArray("shift", (LazyArray._wrap(node),), value=(int(k), float(fill)))
+
+
 def dot(a, b, out=None, stream=None):
     return (LazyArray._wrap(a) * LazyArray._wrap(b)).sum(out=out, stream=stream)
 
@@ -128,16 +141,22 @@ def render(node: LazyArray):
     leaves = node.leaves()
     index = {id(t): k for k, t in enumerate(leaves)}
 
-    def text(n):
+    def text(n, at=0):            # the subtree at index i + at
+        idx = "i" if at == 0 else (f"i + {at}" if at > 0 else f"i - {-at}")
         if n.op == "leaf":
-            return f"(float)a{index[id(n.tensor)]}[i]"
+            return f"(float)a{index[id(n.tensor)]}[{idx}]"
         if n.op == "const":
             return _float_literal(n.value)
+        if n.op == "shift":
+            k, fill = n.value
+            j = at + k
+            jdx = "i" if j == 0 else (f"i + {j}" if j > 0 else f"i - {-j}")
+            return f"({jdx} >= 0 && {jdx} < n ? {text(n.args[0], j)} : {_float_literal(fill)})"
         if n.op == "neg":
-            return f"(-{text(n.args[0])})"
+            return f"(-{text(n.args[0], at)})"
         if n.op in _BINARY:
-            return f"({text(n.args[0])} {_BINARY[n.op]} {text(n.args[1])})"
-        return f"{_FUNCS[n.op]}({', '.join(text(a) for a in n.args)})"
+            return f"({text(n.args[0], at)} {_BINARY[n.op]} {text(n.args[1], at)})"
+        return f"{_FUNCS[n.op]}({', '.join(text(a, at) for a in n.args)})"
     return text(node), leaves
 
 
@@ -197,7 +216,7 @@ def _evaluate_unfused(node, out, stream):
         if n.op in ("leaf", "const"):
             return n
         kids = [ev(a) for a in n.args]
-        sub = LazyArray(n.op, kids)
+        sub = LazyArray(n.op, kids, value=n.value)
         arrays = [k for k in kids if k.op == "leaf"]
         if not arrays:
             raise ValueError("an expression needs at least one array")
@@ -224,4 +243,4 @@ def _reduce(node, combine, neutral, out, stream):
 
 
 __all__ = ["LazyArray", "lazy", "evaluate", "render", "elementwise_source", "reduce_source",
-           "dot", "sqrt", "exp", "log", "sin", "cos", "abs", "maximum", "minimum"]
+           "dot", "shift", "sqrt", "exp", "log", "sin", "cos", "abs", "maximum", "minimum"]

@@ -59,3 +59,18 @@ def test_lazy_reductions(dev, red):
     order = [next(k for k, d in enumerate(ds) if d is t) for t in lv]
     r = oracle.reduce(dtypes, expr, comb, neu, n, host_arrays([ts[k] for k in order]))
     assert_reduce(out, r, red)
+
+
+def test_lazy_shifted_reduction(dev):
+    # total variation sum |x[i] - x[i+1]| (x[n] read as x[n-1]'s fill of 0):
+    # the map's shifted read takes the reduce kernel's shifted chunk loads
+    n = 300007
+    ts = leaves(n, 13)
+    ds = [t.to(dev) for t in ts]
+    x = lz.lazy(ds[0])
+    node = lz.abs(x - lz.shift(x, 1))
+    out = node.sum()
+    torch.cuda.synchronize()
+    dtypes, expr, lv = lz.reduce_source(node)
+    r = oracle.reduce(dtypes, expr, "a+b", "0", n, host_arrays([ts[0]]))
+    assert_reduce(out, r, "total variation")

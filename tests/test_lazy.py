@@ -21,6 +21,14 @@ def np_eval(node, env):
         return env[id(node.tensor)]
     if node.op == "const":
         return np.float64(np.float32(node.value))
+    if node.op == "shift":                        # the child at i + k, fill outside [0, n)
+        k, fill = node.value
+        a = np.broadcast_to(np_eval(node.args[0], env), (env["n"],))
+        out = np.full(env["n"], np.float64(np.float32(fill)))
+        lo, hi = max(0, -k), min(env["n"], env["n"] - k)
+        if lo < hi:
+            out[lo:hi] = a[lo + k:hi + k]
+        return out
     a = [np_eval(x, env) for x in node.args]
     ops = {"+": np.add, "-": np.subtract, "*": np.multiply, "/": np.divide, "neg": np.negative,
            "sqrt": np.sqrt, "exp": np.exp, "log": np.log, "sin": np.sin, "cos": np.cos,
@@ -48,6 +56,8 @@ EXPRS = {
     "ratio": lambda x, y, w: (x - y) / (w + 1.0) + lz.maximum(x, w) - lz.minimum(y, 0.75),
     "trans": lambda x, y, w: lz.exp(-x) * lz.sin(y) + lz.log(w) * lz.cos(x) - lz.exp(y - w),
     "reuse": lambda x, y, w: (x + x) * (x - 3) + lz.abs(-y),
+    "stencil": lambda x, y, w: (x - 0.5 * (lz.shift(x, -1) + lz.shift(x, 1))
+                                + lz.shift(y * w + lz.shift(w, -2), 3, fill=2.0)),
 }
 
 
@@ -59,6 +69,7 @@ def test_rendered_statement_is_the_tree(name, dts):
     node = EXPRS[name](*(lz.lazy(t) for t in ts))
     dtypes, stmt, lv = lz.elementwise_source(node)
     env = {id(t): t.to(torch.float64).numpy() for t in ts}
+    env["n"] = n
     want = np_eval(node, env)
     arrays = [np.zeros(n, np.float32)] + [
         t.view(torch.int16).numpy().view(np.uint16) if t.dtype == torch.bfloat16 else t.numpy() for t in lv]
@@ -83,6 +94,19 @@ def test_reduce_source_and_errors():
         _ = x + "a"
     with pytest.raises(ValueError):
         lz.lazy(torch.zeros(2, 2))
+
+
+def test_shift_renders_shifted_reads():
+    x, y, _ = (lz.lazy(t) for t in leaves(10, 3))
+    node = x - 0.5 * (lz.shift(x, -1) + lz.shift(x, 1))
+    dtypes, stmt, lv = lz.elementwise_source(node)
+    assert "a0[i - 1]" in stmt and "a0[i + 1]" in stmt and "i - 1 >= 0" in stmt
+    k = hm.compile(stmt, dtypes)
+    assert k.vectorizable and "hipmr_loadu" in k.source(0)     # shifted chunk loads
+    nested = lz.shift(lz.shift(y, 2) * x, -5, fill=1.0)          # distances add up
+    assert "a0[i - 3]" in lz.render(nested)[0] and "a1[i - 5]" in lz.render(nested)[0]
+    with pytest.raises(TypeError):
+        lz.shift(x, 1.5)
 
 
 def test_same_tree_same_kernel():
