@@ -83,3 +83,18 @@ def test_complex_prefix_scan(dev):
     # depth of the scan's combination tree at this size (see the float scan tests)
     tol = 80 * 2.0 ** -24 * r.abs_prefix + 2 * r.err_prefix
     assert np.all(np.abs(g - r.values) <= tol)
+
+
+def test_complex_shifted_reads(dev):
+    # complex64 shifted reads take the vector kernel's unaligned chunk loads
+    n = 70001
+    x, y = cdata(n + 2, 5)
+    sig = "complex64 *z, const complex64 *x, const complex64 *y"
+    stmt = "z[i] = (i >= 1 ? x[i - 1] : y[i]) * conj(x[i]) + (i + 2 < n ? y[i + 2] : x[i])"
+    k = hm.compile(stmt, sig, name="cplx_shift")
+    assert k.vectorizable and "hipmr_loadu" in k.source(0)
+    zd = torch.full((n + 2,), complex("nan+nanj"), dtype=torch.complex64, device=dev)
+    hm.elementwise(k, n, [zd[1:n + 1], dev_array(x)[1:n + 1], dev_array(y)[1:n + 1]])
+    torch.cuda.synchronize()
+    ref = oracle.elementwise(sig, stmt, n, [np.zeros(n, np.complex64), x[1:n + 1], y[1:n + 1]])
+    assert_lanes(zd[1:n + 1], ref["z"], "complex64", what="complex shifted reads")

@@ -506,3 +506,25 @@ def test_shifted_maps(dev, offset):
     hm.scan(hs, "a+b", "0", n, [kd], sc)
     torch.cuda.synchronize()
     assert np.array_equal(host_bits(sc), oracle.scan(ssig, smp, "a+b", "0", n, [ks]).values)
+
+
+def test_fp8_shifted_reads(dev):
+    """FP8 arrays read at a distance (16 values per chunk, loaded by memcpy)."""
+    n = 65537
+    rng = np.random.default_rng(77)
+    bits = rng.integers(0, 256, n + 16).astype(np.uint8)
+    bits[(bits & 0x7F) == 0x7F] = 0x3C                     # no NaN codes
+    sig = "float *z, const fp8_e4m3 *q"
+    stmt = "z[i] = (i + 3 < n ? (float)q[i + 3] : 0.0f) - (i >= 17 ? (float)q[i - 17] : 1.0f) * (float)q[i]"
+    k = hm.compile(stmt, sig, name="fp8_shift")
+    assert k.vectorizable and k.vec == 16
+    qd = dev_array(bits, "fp8_e4m3")
+    outs = []
+    for cfg in (None, {"flags": hm.CFG_FORCE_SCALAR}):
+        z = torch.zeros(n, dtype=torch.float32, device=dev)
+        hm.elementwise(k, n, [z, qd[5:n + 5]], config=cfg)
+        torch.cuda.synchronize()
+        outs.append(host_bits(z))
+    assert np.array_equal(outs[0], outs[1]), "vector and one-element kernels differ"
+    ref = oracle.elementwise(sig, stmt, n, [np.zeros(n, np.float32), bits[5:n + 5]])
+    assert_lanes(z, ref["z"], "float32", what="fp8 shifted reads")
