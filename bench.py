@@ -419,8 +419,8 @@ def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
-              "multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (--gpus {args.gpus} requested); how the path "
+              "would shard across GPUs is described, not measured", file=sys.stderr)
         sys.exit(2)
 
     import torch
