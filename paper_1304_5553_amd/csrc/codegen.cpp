@@ -362,9 +362,10 @@ __device__ __forceinline__ void hipmr_loadu(hipmr_pack<T, N>& p, const T* src) {
 // XCD-aware order: workgroups go round-robin to the 8 XCDs, each with its own
 // L2.  Renumbered, each XCD takes a contiguous run of chunks, so the
 // neighbouring elements a shifted read reaches were loaded by the same XCD.
-// a V-element window start clamped into [0, hi] (hi = n - V >= 0)
-__device__ __forceinline__ long long hipmr_clampv(long long o, long long hi) {
-  return o < 0 ? 0 : (o > hi ? hi : o);
+// the window start off + s clamped into [0, hi] (hi = n - V >= 0, 0 <= off <= hi),
+// without forming off + s when it would leave that range (s may be huge)
+__device__ __forceinline__ long long hipmr_clampv(long long off, long long s, long long hi) {
+  return s < -off ? 0 : (s > hi - off ? hi : off + s);
 }
 
 __device__ __forceinline__ unsigned hipmr_xcd_block() {
@@ -405,8 +406,8 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
       const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       const long long hipmr_off = hipmr_h + hipmr_c * HIPMR_V;
-      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_off + hipmr_smin >= 0 &&
-                           hipmr_off + HIPMR_V + hipmr_smax <= hipmr_n;
+      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_smin >= -hipmr_off &&
+                           hipmr_smax <= hipmr_n - HIPMR_V - hipmr_off;   // no overflow for any distance
       if (hipmr_vec[hipmr_u]) {
         @@LOADS@@
         @@SHIFT_LOADS@@
@@ -591,8 +592,8 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
       const long long hipmr_c = hipmr_c0 + hipmr_u * HIPMR_B;
       const long long hipmr_off = hipmr_c < hipmr_nc ? hipmr_h + hipmr_c * HIPMR_V : hipmr_h;
-      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_off + hipmr_smin >= 0 &&
-                           hipmr_off + HIPMR_V + hipmr_smax <= hipmr_n;
+      hipmr_vec[hipmr_u] = hipmr_c < hipmr_nc && hipmr_smin >= -hipmr_off &&
+                           hipmr_smax <= hipmr_n - HIPMR_V - hipmr_off;   // no overflow for any distance
       @@LOADS@@
       @@SHIFT_LOADS@@
     }
@@ -1507,7 +1508,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             // the reduce kernel loads every chunk (clamped into the array);
             // the elementwise kernel loads only chunks it evaluates as vectors
             const std::string at = spec.kind == KernelKind::RedS1Vector
-                                       ? "hipmr_clampv(hipmr_off + hipmr_s" + k + ", hipmr_n - HIPMR_V)"
+                                       ? "hipmr_clampv(hipmr_off, hipmr_s" + k + ", hipmr_n - HIPMR_V)"
                                        : "hipmr_off + hipmr_s" + k;
             shift_loads += "hipmr_loadu(hipmr_q" + k + "[hipmr_u], " + a.name + " + " + at + "); ";
         }

@@ -107,7 +107,7 @@ def test_shifted_reads_classification():
     # maps: the plain reduce loads shifted reads as chunks too
     r = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f) - x[i]", "float: const float *x")
     assert r.vectorizable
-    assert ("hipmr_loadu(hipmr_q0[hipmr_u], x + hipmr_clampv(hipmr_off + hipmr_s0, hipmr_n - HIPMR_V))"
+    assert ("hipmr_loadu(hipmr_q0[hipmr_u], x + hipmr_clampv(hipmr_off, hipmr_s0, hipmr_n - HIPMR_V))"
             in r.source(2, "a+b", "0"))
 
 

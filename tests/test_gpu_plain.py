@@ -528,3 +528,25 @@ def test_fp8_shifted_reads(dev):
     assert np.array_equal(outs[0], outs[1]), "vector and one-element kernels differ"
     ref = oracle.elementwise(sig, stmt, n, [np.zeros(n, np.float32), bits[5:n + 5]])
     assert_lanes(z, ref["z"], "float32", what="fp8 shifted reads")
+
+
+def test_shifted_reads_huge_distances(dev):
+    """Distances near the 64-bit limits: no chunk qualifies for the vector
+    loads (the bounds checks never form an overflowing sum), every element
+    runs the statement with its own guard."""
+    n = 10007
+    rng = np.random.default_rng(501)
+    x = rng.uniform(-1, 1, n).astype(np.float32)
+    xd = dev_array(x)
+    sig = "float *z, const float *x, long k"
+    stmt = "z[i] = (i + k < n && i + k >= 0 ? x[i + k] : 2.0f) + x[i]"
+    k = hm.compile(stmt, sig, name="shift_huge")
+    rsig, rmap = "float: const float *x, long k", "(i + k < n && i + k >= 0 ? x[i + k] : 2.0f) * x[i]"
+    r = hm.compile(rmap, rsig, name="shift_huge_r")
+    for dist in ((1 << 62), -(1 << 62), (1 << 63) - (1 << 15), -(1 << 63) + (1 << 15)):   # i + k fits
+        z = torch.zeros(n, dtype=torch.float32, device=dev)
+        hm.elementwise(k, n, [z, xd, dist])
+        out = reduce_on_gpu(r, "a+b", "0", n, [xd, dist])
+        torch.cuda.synchronize()
+        assert np.array_equal(host_bits(z), (np.float32(2.0) + x).astype(np.float32)), dist
+        assert_reduce(out, oracle.reduce(rsig, rmap, "a+b", "0", n, [x, np.int64(dist)]), f"reduce {dist}")
