@@ -414,20 +414,23 @@ typedef struct hipmr_server *hipmr_server_t;
 size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
 
 /* Serving extension of the map-reduce: starts a request loop on a host thread
- * for the current device.  The loop releases arrivals, admits them while the
- * bytes of admitted, unfinished jobs stay within the budget (no job is
- * admitted while an earlier one does not fit; small jobs may pass a large one),
- * spreads admitted jobs over the free streams, one batch per stream (continuous
- * batching: jobs that arrive while others run join the next batch on a free
- * stream; one job per free stream while at most batch_backlog jobs per free
- * stream wait, else ceil(waiting / free streams) jobs per batch; a job over
- * solo_bytes runs alone and small jobs are packed past it; a job of at most
- * 16 tiles alone runs in one launch, one block computing and folding its
- * tiles, unless max_batch_jobs is 1) and
- * launches it as two run-time compiled kernels: a persistent kernel whose
- * waves take tiles of any job (wave-uniform switch over template x dtype) and
- * one block per job folding its tiles in a fixed order.  A job's tiles depend
- * only on the job, so its result is bitwise the same alone or in any mix.
+ * for the current device.  The loop
+ *   - releases arrivals at their time;
+ *   - admits them while the bytes of admitted, unfinished jobs stay within
+ *     the budget (no job is admitted while an earlier one does not fit;
+ *     small jobs may pass a large one);
+ *   - hands admitted jobs to the free streams, one batch per stream
+ *     (continuous batching: jobs that arrive while others run join the next
+ *     batch): one job per free stream while at most batch_backlog jobs per
+ *     free stream wait, else ceil(waiting / free streams) jobs per batch; a
+ *     job over solo_bytes runs alone and small jobs are packed past it;
+ *   - launches a batch as two run-time compiled kernels: a persistent kernel
+ *     whose waves take tiles of any job (wave-uniform switch over template x
+ *     dtype) and one block per job folding its tiles in a fixed order.  A job
+ *     of at most 16 tiles alone runs in one launch (one block computes and
+ *     folds its tiles) unless max_batch_jobs is 1.
+ * A job's tiles depend only on the job, so its result is bitwise the same
+ * alone or in any mix.
  * Completion is observed through per-job flags in mapped host memory that the
  * folding block writes after the result (a stream query is the watchdog for
  * errors).  Inputs stay resident: jobs name device arrays.  The server
