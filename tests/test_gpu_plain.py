@@ -313,7 +313,16 @@ def test_64bit_index_beyond_2_31(dev):
     k = hm.compile("(long)i", "long: const uint8_t *x")
     out = reduce_on_gpu(k, "a+b", "0", n, [ones])
     assert out.item() == n * (n - 1) // 2
-    del ones
+    # shifted reads with a 64-bit index: chunk loads near and beyond 2^31
+    k = hm.compile("(i + 3 < n ? x[i + 3] : 0) + (i >= 7 ? x[i - 7] : 0)", "long: const uint8_t *x")
+    assert k.vectorizable
+    out = reduce_on_gpu(k, "a+b", "0", n, [ones])
+    assert out.item() == (n - 3) + (n - 7)
+    e = hm.compile("z[i] = i + 1 < n ? x[i + 1] : 0", "uint8_t *z, const uint8_t *x")
+    z = torch.full((n,), 7, dtype=torch.uint8, device=dev)
+    hm.elementwise(e, n, [z, ones])
+    assert int(z.sum(dtype=torch.int64).item()) == n - 1 and int(z[-1].item()) == 0
+    del ones, z
     torch.cuda.empty_cache()
 
 
