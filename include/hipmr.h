@@ -484,6 +484,19 @@ hipmr_status hipmr_get_handle_info(hipmr_handle h, hipmr_handle_info *info);
 hipmr_status hipmr_get_arg_info(hipmr_handle h, int32_t k, int32_t *dtype, int32_t *is_pointer,
                                 int32_t *is_const, int32_t *is_read, int32_t *is_written);
 
+/* How the expression indexes declared argument k (bit flags, as the classifier
+ * sees it): HIPMR_ACCESS_INDEX name[i] (read or written), HIPMR_ACCESS_SHIFTED
+ * name[i +/- E] with E uniform, HIPMR_ACCESS_FIXED name[<integer literal>],
+ * HIPMR_ACCESS_OTHER any other index or a bare pointer.  An array with INDEX
+ * or SHIFTED access must hold at least n elements (the binding checks this);
+ * one with only FIXED access needs only the elements it names.  0 for a
+ * scalar argument.  Errors: E_INVALID (NULL, k out of range). */
+#define HIPMR_ACCESS_INDEX   1
+#define HIPMR_ACCESS_SHIFTED 2
+#define HIPMR_ACCESS_FIXED   4
+#define HIPMR_ACCESS_OTHER   8
+hipmr_status hipmr_get_arg_access(hipmr_handle h, int32_t k, int32_t *access);
+
 /* Generated HIP source of one kernel variant (for inspection and tests).
  *   kind: 0 elementwise (vector), 1 elementwise (scalar), 2 reduce stage 1
  *         (vector), 3 reduce stage 1 (scalar), 4 reduce stage 2.

@@ -560,6 +560,17 @@ hipmr_status hipmr_get_arg_info(hipmr_handle h, int32_t k, int32_t* dtype, int32
     return HIPMR_OK;
 }
 
+hipmr_status hipmr_get_arg_access(hipmr_handle h, int32_t k, int32_t* access) {
+    clear_error();
+    if (!h || !access) return fail(HIPMR_E_INVALID, "NULL argument");
+    if (k < 0 || k >= (int32_t)h->prog.sig.args.size()) return fail(HIPMR_E_INVALID, "argument index out of range");
+    const ArgDecl& a = h->prog.sig.args[k];
+    *access = (a.lane ? HIPMR_ACCESS_INDEX : 0) |
+              (a.shifted ? HIPMR_ACCESS_SHIFTED : 0) | (a.uniform ? HIPMR_ACCESS_FIXED : 0) |
+              (a.other ? HIPMR_ACCESS_OTHER : 0);
+    return HIPMR_OK;
+}
+
 hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char* combine,
                                      const char* neutral, char* buf, size_t cap, size_t* len) {
     clear_error();

@@ -47,6 +47,7 @@ struct ArgDecl {
     bool lane = false;        // accessed as name[i]
     bool uniform = false;     // read as name[<integer literal>] (the same element for every i)
     bool shifted = false;     // read as name[i + E] / name[i - E], E uniform (see ShiftRead)
+    bool other = false;       // accessed at any other index (or used as a bare pointer)
 };
 
 // An array the vector kernels move in 16-byte chunks (accessed as name[i] or

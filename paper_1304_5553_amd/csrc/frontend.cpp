@@ -315,7 +315,7 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
     std::map<std::string, size_t> arg_index;
     for (size_t a = 0; a < sig->args.size(); ++a) {
         sig->args[a].read = sig->args[a].written = sig->args[a].write_only = false;
-        sig->args[a].lane = sig->args[a].uniform = sig->args[a].shifted = false;
+        sig->args[a].lane = sig->args[a].uniform = sig->args[a].shifted = sig->args[a].other = false;
         arg_index[sig->args[a].name] = a;
     }
     // balance of brackets; forbidden constructs
@@ -392,6 +392,7 @@ hipmr_status classify(const std::vector<Token>& toks, Signature* sig, bool is_ma
             if (!known) out->shifts.push_back(ShiftRead{it->second, offset});
         } else {
             out->vectorizable = false;
+            a.other = true;
             if (!(k + 1 < toks.size() && is_punct(toks[k + 1], "["))) {
                 // bare array name (pointer arithmetic etc.): treat as read and write
                 a.read = true;

@@ -32,6 +32,7 @@ DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "i
 
 CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
 CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES, CFG_SEG_GLOBAL = 8, 16, 32
+ACCESS_INDEX, ACCESS_SHIFTED, ACCESS_FIXED, ACCESS_OTHER = 1, 2, 4, 8
 
 
 class HipmrError(RuntimeError):
@@ -143,6 +144,7 @@ _SIGS = {
     "hipmr_release": (None, [_VP]),
     "hipmr_get_handle_info": (_I32, [_VP, ctypes.POINTER(HandleInfo)]),
     "hipmr_get_arg_info": (_I32, [_VP, _I32] + [ctypes.POINTER(_I32)] * 5),
+    "hipmr_get_arg_access": (_I32, [_VP, _I32, ctypes.POINTER(_I32)]),
     "hipmr_get_kernel_source": (_I32, [_VP, _I32, _CP, _CP, _CP, _SZ, ctypes.POINTER(_SZ)]),
     "hipmr_get_last_symbols": (_I32, [_VP, _CP, _SZ, ctypes.POINTER(_SZ)]),
     "hipmr_get_cache_stats": (_I32, [ctypes.POINTER(CacheStats)]),
@@ -222,7 +224,7 @@ def _lowp_bits(code, value):
 
 
 class Arg:
-    __slots__ = ("name", "dtype", "pointer", "const", "read", "written")
+    __slots__ = ("name", "dtype", "pointer", "const", "read", "written", "access")
 
 
 class Kernel:
@@ -250,6 +252,9 @@ class Kernel:
             _check(lib().hipmr_get_arg_info(h, k, *[ctypes.byref(v) for v in vals]))
             a = Arg()
             a.dtype, a.pointer, a.const, a.read, a.written = (v.value for v in vals)
+            acc = _I32()
+            _check(lib().hipmr_get_arg_access(h, k, ctypes.byref(acc)))
+            a.access = acc.value
             self.args.append(a)
         names = [d.strip().replace("*", " ").split()[-1]
                  for d in dtypes.split(":", 1)[-1].split(",") if d.strip()]
@@ -265,6 +270,16 @@ class Kernel:
         if h is not None and h.value and _lib is not None:
             _lib.hipmr_release(h)
             self._h = None
+
+    def check_lengths(self, n, args):
+        """Arrays the kernels read or write at i or i +/- E must hold at least
+        n elements (section "Efficient Evaluation of Element-wise
+        Expressions": the operands of one call share a length); arrays read
+        only at fixed indices may be shorter."""
+        for decl, val in zip(self.args, args):
+            if decl.pointer and decl.access & (ACCESS_INDEX | ACCESS_SHIFTED) and hasattr(val, "numel"):
+                if val.numel() < n:
+                    raise InvalidError(f"array '{decl.name}' has {val.numel()} elements, fewer than n = {n}")
 
     def marshal(self, args):
         """(keep-alive list, ctypes array of pointers) for the C ABI's args."""
@@ -314,6 +329,7 @@ def compile(expr, dtypes, name=None) -> Kernel:   # noqa: A001 - the C ABI's nam
 
 
 def elementwise(handle: Kernel, n, args, stream=None, config=None):
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_elementwise_ex(handle.handle, int(n), ptrs, _config(config),
                                       _stream_ptr(stream)))
@@ -346,6 +362,7 @@ def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspac
     need = reduce_workspace_bytes(handle, n)
     if workspace_buf is None:
         workspace_buf = workspace(need, out.device, s)
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_reduce_ex(handle.handle, _enc(map_expr), _enc(combine_op), _enc(neutral),
                                  int(n), ptrs, ctypes.c_void_p(out.data_ptr()),
@@ -370,6 +387,7 @@ def reduce_compensated(handle: Kernel, n, args, post_scale=1.0, out=None, worksp
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_reduce_compensated(handle.handle, int(n), ptrs, float(post_scale),
                                           ctypes.c_void_p(out.data_ptr()),
@@ -385,6 +403,7 @@ def norm2(handle: Kernel, n, args, post_scale=1.0, passes=2, out=None, workspace
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_norm2(handle.handle, int(n), ptrs, float(post_scale), int(passes),
                              ctypes.c_void_p(out.data_ptr()),
@@ -404,6 +423,7 @@ def scan(handle: Kernel, combine_op, neutral, n, args, out, exclusive=False, wor
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(scan_workspace_bytes(handle, n), out.device, s)
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_scan(handle.handle, combine_op.encode(), neutral.encode(), int(n), ptrs,
                             ctypes.c_void_p(out.data_ptr()), 1 if exclusive else 0,
@@ -424,6 +444,7 @@ def reduce_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, args
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
+    handle.check_lengths(int(total_n), args)
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_reduce_segmented(handle.handle, combine_op.encode(), neutral.encode(), nseg,
                                         ctypes.c_void_p(offsets.data_ptr()), int(total_n), ptrs,
@@ -441,6 +462,7 @@ def autotune_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, ar
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
+    handle.check_lengths(int(total_n), args)
     keep, ptrs = handle.marshal(args)
     best = LaunchConfig()
     _check(lib().hipmr_autotune_segmented(handle.handle, combine_op.encode(), neutral.encode(), nseg,
@@ -456,6 +478,7 @@ def autotune_reduce(handle: Kernel, combine_op, neutral, n, args, out, reps=10,
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
+    handle.check_lengths(int(n), args)
     keep, ptrs = handle.marshal(args)
     best = LaunchConfig()
     _check(lib().hipmr_autotune_reduce(handle.handle, combine_op.encode(), neutral.encode(), int(n),

@@ -111,6 +111,25 @@ def test_shifted_reads_classification():
             in r.source(2, "a+b", "0"))
 
 
+def test_argument_access_flags_and_length_check():
+    import torch
+    A = hm.hipmr
+    k = hm.compile("x[i] += (float)a[0] * p[i] + (i >= 1 ? p[i - 1] : 0.0f) + q[n - 1 - i]",
+                   "float *x, const float *p, const double *a, const float *q")
+    assert [a.access for a in k.args] == [A.ACCESS_INDEX, A.ACCESS_INDEX | A.ACCESS_SHIFTED,
+                                         A.ACCESS_FIXED, A.ACCESS_OTHER]
+    # arrays indexed by i (or i +/- E) need n elements; fixed-element arrays do not
+    x, p, a, q = torch.zeros(10), torch.zeros(10), torch.zeros(1, dtype=torch.float64), torch.zeros(3)
+    k.check_lengths(10, [x, p, a, q])
+    with pytest.raises(hm.InvalidError, match="'p' has 9 elements"):
+        k.check_lengths(10, [x, p[:9], a, q])
+    s = hm.compile("(i + 2 < n ? y[i + 2] : 0.0f)", "float: const float *y")
+    assert s.args[0].access == A.ACCESS_SHIFTED
+    with pytest.raises(hm.InvalidError):
+        s.check_lengths(11, [torch.zeros(10)])
+    assert hm.compile("x[i]", "float: const float *x, float c").args[1].access == 0   # a scalar
+
+
 def test_generated_source_shape():
     k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y",
                    name="lin")
