@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import struct
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -200,6 +201,11 @@ def _config(cfg):
     return ctypes.byref(c)
 
 
+_PACK = {F32: "<f", F64: "<d"}
+_INT_MASK = {I8: 0xFF, U8: 0xFF, I16: 0xFFFF, U16: 0xFFFF, I32: 0xFFFFFFFF, U32: 0xFFFFFFFF,
+             I64: 0xFFFFFFFFFFFFFFFF}
+_CTYPE_F32 = ctypes.c_float
+
 _CTYPE = {F32: ctypes.c_float, F64: ctypes.c_double, I8: ctypes.c_int8, U8: ctypes.c_uint8,
           I16: ctypes.c_int16, U16: ctypes.c_uint16, I32: ctypes.c_int32, U32: ctypes.c_uint32,
           I64: ctypes.c_int64, BF16: ctypes.c_uint16, F16: ctypes.c_uint16, FP8: ctypes.c_uint8,
@@ -260,6 +266,9 @@ class Kernel:
                  for d in dtypes.split(":", 1)[-1].split(",") if d.strip()]
         for a, nm in zip(self.args, names):
             a.name = nm
+        # arrays that must hold n elements (accessed at i or i +/- E)
+        self._sized = [k for k, a in enumerate(self.args)
+                       if a.pointer and a.access & (ACCESS_INDEX | ACCESS_SHIFTED)]
 
     @property
     def handle(self):
@@ -276,31 +285,36 @@ class Kernel:
         n elements (section "Efficient Evaluation of Element-wise
         Expressions": the operands of one call share a length); arrays read
         only at fixed indices may be shorter."""
-        for decl, val in zip(self.args, args):
-            if decl.pointer and decl.access & (ACCESS_INDEX | ACCESS_SHIFTED) and hasattr(val, "numel"):
-                if val.numel() < n:
-                    raise InvalidError(f"array '{decl.name}' has {val.numel()} elements, fewer than n = {n}")
+        for k in self._sized:
+            val = args[k] if k < len(args) else None
+            if hasattr(val, "numel") and val.numel() < n:
+                raise InvalidError(f"array '{self.args[k].name}' has {val.numel()} elements, "
+                                   f"fewer than n = {n}")
 
     def marshal(self, args):
-        """(keep-alive list, ctypes array of pointers) for the C ABI's args."""
+        """(keep-alive storage, ctypes array of pointers) for the C ABI's args:
+        every value sits in its own 8-byte slot of one buffer (a device
+        pointer, or the scalar's bytes in its C type), and args[k] points at
+        slot k."""
         if len(args) != len(self.args):
             raise InvalidError(f"expected {len(self.args)} arguments, got {len(args)}")
-        keep = []
-        ptrs = (ctypes.c_void_p * max(1, len(args)))()
+        nargs = max(1, len(args))
+        store = (ctypes.c_uint64 * nargs)()
         for k, (decl, val) in enumerate(zip(self.args, args)):
             if decl.pointer:
-                p = val if isinstance(val, int) else (0 if val is None else val.data_ptr())
-                c = ctypes.c_void_p(p)
+                store[k] = val if isinstance(val, int) else (0 if val is None else val.data_ptr())
             elif decl.dtype in (BF16, F16, FP8):
-                c = _CTYPE[decl.dtype](_lowp_bits(decl.dtype, val))
+                store[k] = _lowp_bits(decl.dtype, val)
             elif decl.dtype == C64:
                 z = complex(val)
-                c = _CTYPE[C64](z.real, z.imag)
-            else:
-                c = _CTYPE[decl.dtype](val)
-            keep.append(c)
-            ptrs[k] = ctypes.cast(ctypes.byref(c), ctypes.c_void_p)
-        return keep, ptrs
+                struct.pack_into("<ff", store, 8 * k, _CTYPE_F32(z.real).value, _CTYPE_F32(z.imag).value)
+            elif decl.dtype in _INT_MASK:              # C conversion: wrap to the width
+                store[k] = int(val) & _INT_MASK[decl.dtype]
+            else:                                      # float / double, as C converts them
+                struct.pack_into(_PACK[decl.dtype], store, 8 * k, _CTYPE[decl.dtype](val).value)
+        base = ctypes.addressof(store)
+        ptrs = (ctypes.c_void_p * nargs)(*range(base, base + 8 * nargs, 8))
+        return store, ptrs
 
     def last_symbols(self):
         """Symbols of the kernels the last call on this handle launched."""

@@ -130,6 +130,28 @@ def test_argument_access_flags_and_length_check():
     assert hm.compile("x[i]", "float: const float *x, float c").args[1].access == 0   # a scalar
 
 
+def test_marshal_holds_each_value_in_its_c_type():
+    # args[k] points at the bytes of argument k as its C type (wrapping
+    # integers, float overflow to inf, low-precision scalars rounded once)
+    import torch
+    B = hm.hipmr
+    sig = ("float *z, float a, double b, char c, unsigned char d, short e, unsigned short f, int g, "
+           "unsigned h, long l, bfloat16 m, half o, fp8_e4m3 q, complex64 r")
+    k = hm.compile("z[i] = a", sig)
+    vals = [torch.zeros(4), 1.0e300, -2.5, -3, 300, -40000, 70000, 2 ** 31 + 5, -1, -(2 ** 40), 1.5,
+            131008.0, 500.0, 0.25 - 1.5j]
+    store, ptrs = k.marshal(vals)
+    want = [ctypes.c_void_p(vals[0].data_ptr()), ctypes.c_float(vals[1]), ctypes.c_double(vals[2]),
+            ctypes.c_int8(vals[3]), ctypes.c_uint8(vals[4]), ctypes.c_int16(vals[5]),
+            ctypes.c_uint16(vals[6]), ctypes.c_int32(vals[7]), ctypes.c_uint32(vals[8]),
+            ctypes.c_int64(vals[9]), ctypes.c_uint16(0x3FC0), ctypes.c_uint16(0x7C00),
+            ctypes.c_uint8(0x7E), (ctypes.c_float * 2)(0.25, -1.5)]
+    for i, w in enumerate(want):
+        assert ctypes.string_at(ptrs[i], ctypes.sizeof(w)) == bytes(w), i
+    with pytest.raises(hm.InvalidError):
+        k.marshal(vals[:-1])
+
+
 def test_generated_source_shape():
     k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y",
                    name="lin")
