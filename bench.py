@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="dot,precision,batched,served,scan,cg,lazy",
+    p.add_argument("--extensions", default="dot,precision,batched,served,scan,shifted,cg,lazy",
                    help="comma list of the extension measurements to run "
-                        "(dot, precision, batched, served, scan, cg, lazy)")
+                        "(dot, precision, batched, served, scan, shifted, cg, lazy)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -150,6 +150,40 @@ def bench_dot(torch, hm, workloads, dev, stream, reps=200):
             "event_us_p50": round(gpu_ms * 1e3, 2),
             "GB/s_async": round(8 * x.size / async_us / 1e3, 1),
             "note": "launch-bound: 8.4 MB is about 1 us of HBM traffic; GB/s is not a roofline claim"}
+
+
+def bench_shifted(torch, hm, dev, stream, reps=20):
+    """Shifted reads name[i +/- E] on the vector kernels against the
+    one-element kernels: the five-point stencil q = A p on a 4096^2 grid
+    (8 B per unknown: p read once, q written; the neighbours come from the
+    caches) and the lag-1 product sum over 2^28 float32 (4 B per element)."""
+    from paper_1304_5553_amd import cg as hcg
+    res = {}
+    nx = 4096
+    m = nx * nx
+    p = torch.rand(m, device=dev)
+    q = torch.empty(m, device=dev)
+    k = hm.compile(hcg.SPMV[1], hcg.SPMV[0], name="cg_spmv")
+    row = {"n": m, "bytes_per_element": 8}
+    for tag, cfg in (("vector", None), ("one_element", {"flags": hm.CFG_FORCE_SCALAR})):
+        ms = _time_ms(torch, lambda: hm.elementwise(k, m, [q, p, nx], config=cfg), reps, stream)
+        row[tag] = {"us": round(ms * 1e3, 2), "GB/s": round(8 * m / ms / 1e6, 1)}
+    row["speedup"] = round(row["one_element"]["us"] / row["vector"]["us"], 2)
+    res["stencil_4096x4096"] = row
+    del p, q
+    n = 1 << 28
+    x = torch.rand(n, device=dev)
+    out = torch.empty((), device=dev)
+    r = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f) * x[i]", "float: const float *x", name="lag1")
+    row = {"n": n, "bytes_per_element": 4}
+    for tag, cfg in (("vector", None), ("one_element", {"flags": hm.CFG_FORCE_SCALAR})):
+        ms = _time_ms(torch, lambda: hm.reduce(r, None, "a+b", "0", n, [x], out, config=cfg), reps, stream)
+        row[tag] = {"us": round(ms * 1e3, 2), "GB/s": round(4 * n / ms / 1e6, 1)}
+    row["speedup"] = round(row["one_element"]["us"] / row["vector"]["us"], 2)
+    res["lag1_sum_2e28"] = row
+    del x
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
@@ -574,6 +608,9 @@ def main():
     if "batched" in ext:
         line["batched"] = bench_batched(torch, hm, workloads, dev)
         print("batched done", file=sys.stderr, flush=True)
+    if "shifted" in ext:
+        line["shifted"] = bench_shifted(torch, hm, dev, stream)
+        print("shifted done", file=sys.stderr, flush=True)
     if "scan" in ext:
         line["scan"] = bench_scan(torch, hm, workloads, dev, stream)
         print("scan done", file=sys.stderr, flush=True)
