@@ -156,12 +156,15 @@ def bench_shifted(torch, hm, dev, stream, reps=20):
     """Shifted reads name[i +/- E] on the vector kernels against the
     one-element kernels: the five-point stencil q = A p on a 4096^2 grid
     (8 B per unknown: p read once, q written; the neighbours come from the
-    caches) and the lag-1 product sum over 2^28 float32 (4 B per element)."""
+    caches) and the lag-1 product sum over 2^28 float32 (4 B per element);
+    inputs U[0, 1) from a device generator seeded with 10."""
     from paper_1304_5553_amd import cg as hcg
     res = {}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(10)
     nx = 4096
     m = nx * nx
-    p = torch.rand(m, device=dev)
+    p = torch.rand(m, device=dev, generator=gen)
     q = torch.empty(m, device=dev)
     k = hm.compile(hcg.SPMV[1], hcg.SPMV[0], name="cg_spmv")
     row = {"n": m, "bytes_per_element": 8}
@@ -172,7 +175,7 @@ def bench_shifted(torch, hm, dev, stream, reps=20):
     res["stencil_4096x4096"] = row
     del p, q
     n = 1 << 28
-    x = torch.rand(n, device=dev)
+    x = torch.rand(n, device=dev, generator=gen)
     out = torch.empty((), device=dev)
     r = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f) * x[i]", "float: const float *x", name="lag1")
     row = {"n": n, "bytes_per_element": 4}

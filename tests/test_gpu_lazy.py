@@ -74,3 +74,27 @@ def test_lazy_shifted_reduction(dev):
     dtypes, expr, lv = lz.reduce_source(node)
     r = oracle.reduce(dtypes, expr, "a+b", "0", n, host_arrays([ts[0]]))
     assert_reduce(out, r, "total variation")
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_lazy_timed_expression_full_size_sampled(dev, fused):
+    # the timed fused expression at its measured size: z = 2.5 x y +
+    # sqrt(x x + y y) - 0.5 w over 2^26 float32 U[-1, 1] values, checked on
+    # both ends and a random sample of lanes
+    n = 1 << 26
+    rng = np.random.default_rng(9)
+    xs = [rng.uniform(-1, 1, n).astype(np.float32) for _ in range(3)]
+    ds = [torch.from_numpy(a).to(dev) for a in xs]
+    x, y, w = (lz.lazy(t) for t in ds)
+    node = 2.5 * x * y + lz.sqrt(x * x + y * y) - 0.5 * w
+    got = node.eval(fused=fused)
+    torch.cuda.synchronize()
+    dtypes, stmt, lv = lz.elementwise_source(node)
+    order = [next(k for k, d in enumerate(ds) if d is t) for t in lv]
+    lanes = np.unique(np.concatenate([np.arange(4096), np.arange(n - 4096, n),
+                                      rng.integers(0, n, 1 << 18)]))
+    ref = oracle.elementwise(dtypes, stmt, n, [np.zeros(1, np.float32)] + [xs[k] for k in order],
+                             lanes=lanes)["out"]
+    assert assert_lanes(got, ref, "float32", what=f"lazy 2^26 fused={fused}") == lanes.size
+    del ds, got
+    torch.cuda.empty_cache()

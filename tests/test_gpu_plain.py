@@ -559,3 +559,38 @@ def test_shifted_reads_huge_distances(dev):
         torch.cuda.synchronize()
         assert np.array_equal(host_bits(z), (np.float32(2.0) + x).astype(np.float32)), dist
         assert_reduce(out, oracle.reduce(rsig, rmap, "a+b", "0", n, [x, np.int64(dist)]), f"reduce {dist}")
+
+
+@pytest.mark.parametrize("flags", [0, hm.CFG_FORCE_SCALAR])
+def test_shifted_reads_at_timed_sizes(dev, flags):
+    # the two timed shifted-read workloads at their measured sizes, on the
+    # vector kernels and on the one-element kernels: the five-point stencil on
+    # a 4096 x 4096 grid (sampled lanes against the oracle) and the lag-1
+    # product sum over 2^28 float32 values of +-1, whose float sum is an exact
+    # integer in any order (every partial sum is an integer far below 2^24)
+    from paper_1304_5553_amd import cg as hcg
+    cfg = {"flags": flags} if flags else None
+    nx = 4096
+    m = nx * nx
+    rng = np.random.default_rng(10)
+    p = rng.random(m, dtype=np.float32)
+    pd, q = dev_array(p), torch.empty(m, device=dev)
+    k = hm.compile(hcg.SPMV[1], hcg.SPMV[0], name="cg_spmv")
+    hm.elementwise(k, m, [q, pd, nx], config=cfg)
+    torch.cuda.synchronize()
+    lanes = np.unique(np.concatenate([np.arange(2 * nx), np.arange(m - 2 * nx, m),
+                                      rng.integers(0, m, 1 << 17)]))
+    ref = oracle.elementwise(hcg.SPMV[0], hcg.SPMV[1], m, [np.zeros(1, np.float32), p, np.int32(nx)],
+                             lanes=lanes)["q"]
+    assert assert_lanes(q, ref, "float32", what=f"stencil 4096^2 flags={flags}") == lanes.size
+    del pd, q
+    n = 1 << 28
+    s = (rng.integers(0, 2, n, dtype=np.int8) * 2 - 1).astype(np.int8)
+    want = int((s[1:] * s[:-1]).sum(dtype=np.int64))
+    xd = dev_array(s.astype(np.float32))
+    r = hm.compile("(i + 1 < n ? x[i + 1] : 0.0f) * x[i]", "float: const float *x", name="lag1")
+    out = reduce_on_gpu(r, "a+b", "0", n, [xd], config=cfg)
+    assert r.last_symbols()[0].split("_")[-2] == ("rs1s" if flags else "rs1")
+    assert out.item() == float(want), (out.item(), want)
+    del xd
+    torch.cuda.empty_cache()

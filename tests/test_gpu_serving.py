@@ -240,3 +240,49 @@ def test_short_queue_runs_one_job_per_stream(dev, pool):
         got = out.cpu().numpy()
         for k in range(0, m, 7):
             oracle_check(k, float(got[k]), sched, pool)
+
+
+@pytest.fixture(scope="module")
+def full_pool(dev):
+    f32, bf16 = workloads.serving_pool()
+    dev_f32 = {k: torch.from_numpy(v).to(dev) for k, v in f32.items()}
+    dev_bf16 = {k: torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).to(dev)
+                for k, v in bf16.items()}
+    return f32, bf16, dev_f32, dev_bf16
+
+
+@pytest.mark.parametrize("rate", [50000, 200000])
+def test_full_size_stream_sampled(dev, full_pool, rate):
+    # the measured serving configuration: a 2^24-element pool per array and
+    # dtype, job sizes log-uniform over [2^10, 2^24], a 64 GiB budget, 4
+    # streams, up to 1024 jobs per launch; a short window of the stream, with
+    # the largest jobs and a random sample checked against the oracle and
+    # against the same job run alone
+    sched = workloads.serving_schedule(rate, 1000 / rate)
+    m = len(sched["n"])
+    out = torch.full((m,), float("nan"), dtype=torch.float64, device=dev)
+    server = hm.Server(hbm_budget_bytes=64 << 30, nstreams=4, max_batch_jobs=1024)
+    done = server.run_schedule(make_jobs(server, sched, full_pool, out))
+    torch.cuda.synchronize()
+    server.close()
+    got = out.cpu().numpy()
+    assert m > 900 and np.all(done["status"] == 0)
+    assert not np.any(np.isnan(got))
+    assert int(np.max(sched["n"])) > (1 << 23)
+    rng = np.random.default_rng(rate)
+    largest = np.argsort(sched["n"])[-3:]
+    pick = np.unique(np.concatenate([largest, rng.choice(m, 12, replace=False)]))
+    for k in pick:
+        oracle_check(int(k), float(got[k]), sched, full_pool)
+    alone_pick = np.unique(np.concatenate([largest, rng.choice(m, 24, replace=False)]))
+    server = hm.Server(hbm_budget_bytes=64 << 30, nstreams=4, max_batch_jobs=1024)
+    alone_out = torch.full((m,), float("nan"), dtype=torch.float64, device=dev)
+    jobs = make_jobs(server, sched, full_pool, alone_out)
+    for k in alone_pick:
+        server.submit(jobs[k].copy())
+        server.wait_idle()
+    torch.cuda.synchronize()
+    server.close()
+    alone = alone_out.cpu().numpy()
+    for k in alone_pick:
+        assert alone[k] == got[k], (rate, int(k), alone[k], got[k])
