@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="dot,precision,batched,served,scan,shifted,cg,lazy",
+    p.add_argument("--extensions", default="dot,precision,batched,served,scan,shifted,cg,lazy,complex",
                    help="comma list of the extension measurements to run "
-                        "(dot, precision, batched, served, scan, shifted, cg, lazy)")
+                        "(dot, precision, batched, served, scan, shifted, cg, lazy, complex)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -324,6 +324,40 @@ def bench_lazy(torch, dev, stream, reps=10):
             "unfused": {"ms": round(unfused_ms, 4), "kernels": kernels, "bytes_per_element": per,
                         "GB/s": round(per * n / unfused_ms / 1e6, 1)},
             "speedup": round(unfused_ms / fused_ms, 2)}
+
+
+def bench_complex(torch, hm, workloads, dev, stream, reps=10):
+    """complex64 at n = 2^27 (1 GiB per array): z = a x + b y with complex
+    scalars (24 B/element), the conjugated dot sum conj(x) y (16 B/element)
+    and the sum of x (8 B/element)."""
+    n = workloads.N_COMPLEX
+    x, y = workloads.complex_xy(n)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    del x, y
+    z = torch.empty_like(xd)
+
+    def row(ms, per, k):
+        gbs = per * n / ms / 1e6
+        return {"ms": round(ms, 4), "bytes_per_element": per, "GB/s": round(gbs, 1),
+                "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "elements_per_s": round(n / ms * 1e3, 1), "symbols": k.last_symbols()}
+
+    res = {"n": n}
+    sig, stmt = workloads.C_AXPBY
+    k = hm.compile(stmt, sig, name="c_axpby")
+    args = [z, workloads.C_A, xd, workloads.C_B, yd]
+    res["axpby"] = row(_time_ms(torch, lambda: hm.elementwise(k, n, args), reps, stream), 24, k)
+    out = torch.empty((), dtype=torch.complex64, device=dev)
+    for name, spec, srcs, per in (("conj_dot", workloads.C_DOT, [xd, yd], 16),
+                                  ("sum", workloads.C_SUM, [xd], 8)):
+        sig, mp, comb, neu = spec
+        k = hm.compile(mp, sig, name=f"c_{name}")
+        ws = hm.hipmr.workspace(hm.reduce_workspace_bytes(k, n), dev, stream.cuda_stream)
+        call = lambda: hm.reduce(k, None, comb, neu, n, srcs, out, workspace_buf=ws)
+        res[name] = row(_time_ms(torch, call, reps, stream), per, k)
+    del xd, yd, z
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
@@ -620,6 +654,9 @@ def main():
     if "lazy" in ext:
         line["lazy"] = bench_lazy(torch, dev, stream)
         print("lazy done", file=sys.stderr, flush=True)
+    if "complex" in ext:
+        line["complex"] = bench_complex(torch, hm, workloads, dev, stream)
+        print("complex done", file=sys.stderr, flush=True)
     if "cg" in ext:
         line["cg"] = bench_cg(torch, hm, dev)
         print("cg done", file=sys.stderr, flush=True)

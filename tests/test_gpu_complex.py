@@ -98,3 +98,43 @@ def test_complex_shifted_reads(dev):
     torch.cuda.synchronize()
     ref = oracle.elementwise(sig, stmt, n, [np.zeros(n, np.complex64), x[1:n + 1], y[1:n + 1]])
     assert_lanes(zd[1:n + 1], ref["z"], "complex64", what="complex shifted reads")
+
+
+def test_complex_at_timed_size(dev):
+    # the timed complex64 workloads at n = 2^27: z = a x + b y on the timed
+    # inputs (sampled lanes against the oracle), then the conjugated dot and
+    # the sum of Gaussian integers with parts in [-3, 3], whose float sums
+    # are exact integers in any order (every partial sum stays far below 2^24)
+    import workloads
+    n = workloads.N_COMPLEX
+    x, y = workloads.complex_xy(n)
+    xd, yd = dev_array(x), dev_array(y)
+    z = torch.empty_like(xd)
+    sig, stmt = workloads.C_AXPBY
+    k = hm.compile(stmt, sig, name="c_axpby")
+    hm.elementwise(k, n, [z, workloads.C_A, xd, workloads.C_B, yd])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    lanes = np.unique(np.concatenate([np.arange(4096), np.arange(n - 4096, n),
+                                      rng.integers(0, n, 1 << 18)]))
+    ref = oracle.elementwise(sig, stmt, n, [np.zeros(1, np.complex64), np.complex64(workloads.C_A), x,
+                                            np.complex64(workloads.C_B), y], lanes=lanes)["z"]
+    assert assert_lanes(z, ref, "complex64", what="complex axpby 2^27") == lanes.size
+    del xd, yd, z, x, y
+    parts = [rng.integers(-3, 4, n).astype(np.int64) for _ in range(4)]
+    xr, xi, yr, yi = parts
+    gx = (xr + 1j * xi).astype(np.complex64)
+    gy = (yr + 1j * yi).astype(np.complex64)
+    xd, yd = dev_array(gx), dev_array(gy)
+    out = torch.empty((), dtype=torch.complex64, device=dev)
+    sig, mp, comb, neu = workloads.C_DOT
+    kd = hm.compile(mp, sig, name="c_conj_dot")
+    got = complex(reduce_on_gpu(kd, comb, neu, n, [xd, yd], out=out).item())
+    want = complex(int((xr * yr + xi * yi).sum()), int((xr * yi - xi * yr).sum()))
+    assert got == want, (got, want)
+    sig, mp, comb, neu = workloads.C_SUM
+    ks = hm.compile(mp, sig, name="c_sum")
+    got = complex(reduce_on_gpu(ks, comb, neu, n, [xd], out=out).item())
+    assert got == complex(int(xr.sum()), int(xi.sum())), got
+    del xd, yd
+    torch.cuda.empty_cache()

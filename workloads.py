@@ -68,6 +68,27 @@ def plain_k(n=N_PLAIN):
     return rng.integers(0, 1 << 20, n, dtype=np.int32)
 
 
+# -------------------------------------------------------------- complex
+N_COMPLEX = 1 << 27
+C_AXPBY = ("complex64 *z, complex64 a, const complex64 *x, complex64 b, const complex64 *y",
+           "z[i] = a*x[i] + b*y[i]")
+C_DOT = ("complex64: const complex64 *x, const complex64 *y", "conj(x[i]) * y[i]", "a+b", "0")
+C_SUM = ("complex64: const complex64 *x", "x[i]", "a+b", "0")
+C_A, C_B = 0.75 - 1.25j, -0.5 + 0.25j
+
+
+def complex_xy(n=N_COMPLEX, seed=11):
+    """x, y complex64 with real and imaginary parts ~ U[-1, 1] float32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(2):
+        v = np.empty(n, np.complex64)
+        v.real = uniform_f32(rng, n)
+        v.imag = uniform_f32(rng, n)
+        out.append(v)
+    return out
+
+
 # -------------------------------------------------------------- precision
 FMAX_SCALE = {"bfloat16": None, "float16": 2.0 ** 15, "fp8_e4m3": 448.0}
 
