@@ -42,9 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extensions", action="store_true",
                    help="skip the precision, batching and serving measurements")
-    p.add_argument("--extensions", default="dot,precision,batched,served,scan,shifted,cg,lazy,complex",
+    p.add_argument("--extensions", default="compile,dot,precision,batched,served,scan,shifted,cg,lazy,complex",
                    help="comma list of the extension measurements to run "
-                        "(dot, precision, batched, served, scan, shifted, cg, lazy, complex)")
+                        "(compile, dot, precision, batched, served, scan, shifted, cg, lazy, complex)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=5.0,
@@ -113,6 +113,80 @@ def _time_ms(torch, fn, reps, stream):
         b.record(stream)
     torch.cuda.synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
+    """Rows a1-a4 on the host: the cost of compile(expr, dtypes) when hipRTC
+    runs (cold), when the code object comes from the disk cache (after the
+    in-memory cache is dropped) and when it is in memory (front end, code
+    generation and the SHA-256 key only), for E1 and for R2's two reduce
+    kernels; then the host time of one elementwise call (argument marshalling
+    and the enqueue) and the GPU time per launch of a 4096-element E1, back to
+    back.  Each cold source is new (its own kernel name) and the disk cache is
+    a fresh directory, so nothing is found by accident."""
+    import shutil
+    import tempfile
+    binding = hm.hipmr
+    saved = os.environ.get("HIPMR_CACHE_DIR")
+    tmp = tempfile.mkdtemp(prefix="hipmr_bench_cache_")
+    os.environ["HIPMR_CACHE_DIR"] = tmp
+    tag = f"{os.getpid()}_{time.time_ns()}"
+    res = {}
+    try:
+        for label, (sig, expr), combine in (("elementwise_E1", workloads.E1, None),
+                                            ("reduce_R2", workloads.R_SUM[:2], workloads.R_SUM[2:])):
+            times = {"cold": [], "disk": [], "memory": []}
+            before = binding.cache_stats()
+            for r in range(reps):
+                name = f"cold{r}_{tag}"
+
+                def build():
+                    k = hm.compile(expr, sig, name=name)
+                    if combine:
+                        binding.prepare_reduce(k, *combine)
+                    return k
+
+                for phase in ("cold", "disk", "memory"):
+                    if phase == "disk":
+                        binding.cache_drop_memory()
+                    t0 = time.perf_counter()
+                    build()
+                    times[phase].append((time.perf_counter() - t0) * 1e3)
+            after = binding.cache_stats()
+            res[label] = {f"{p}_ms_median": round(float(np.median(v)), 4) for p, v in times.items()}
+            res[label]["cache_counts"] = {f: after[f] - before[f]
+                                          for f in ("compiles", "disk_hits", "memory_hits")}
+    finally:
+        if saved is None:
+            os.environ.pop("HIPMR_CACHE_DIR", None)
+        else:
+            os.environ["HIPMR_CACHE_DIR"] = saved
+        shutil.rmtree(tmp, ignore_errors=True)
+    sig, stmt = workloads.E1
+    k = hm.compile(stmt, sig, name="e1_lincomb")
+    n = 4096
+    x = torch.zeros(n, device=dev)
+    y = torch.zeros(n, device=dev)
+    z = torch.empty(n, device=dev)
+    args = [z, x, y]
+    hm.elementwise(k, n, args)
+    torch.cuda.synchronize()
+    host = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        for _ in range(launches):
+            hm.elementwise(k, n, args)
+        host.append((time.perf_counter() - t0) / launches * 1e6)
+        torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(launches):
+        hm.elementwise(k, n, args)
+    b.record(stream)
+    torch.cuda.synchronize()
+    res["launch_E1_4096"] = {"host_us_per_call": round(float(np.median(host)), 2),
+                             "gpu_us_per_launch_back_to_back": round(a.elapsed_time(b) * 1e3 / launches, 2)}
+    return res
 
 
 def bench_dot(torch, hm, workloads, dev, stream, reps=200):
@@ -636,6 +710,9 @@ def main():
     if ext:
         del xd, yd, kd, z
         torch.cuda.empty_cache()
+    if "compile" in ext:
+        line["compile"] = bench_compile(torch, hm, workloads, dev, stream)
+        print("compile done", file=sys.stderr, flush=True)
     if "dot" in ext:
         line["dot"] = bench_dot(torch, hm, workloads, dev, stream)
         print("dot done", file=sys.stderr, flush=True)

@@ -6,7 +6,9 @@
 // the GPU and run.  Only kernels whose source changed are recompiled, so the
 // others load near-instantly.  Here:
 //   key     = SHA-256(source, compiler options, hipRTC version)
-//   memory  = process-wide map key -> code object
+//   memory  = process-wide map (source, options, version) -> code object,
+//             looked up by the text itself, so a hit costs one string hash
+//             and one comparison, and the SHA-256 runs only on a miss
 //   disk    = $HIPMR_CACHE_DIR/<key>.hsaco with a header (magic, payload size,
 //             payload SHA-256) so that truncated or corrupted files are
 //             detected and rebuilt; written to a temporary name and renamed
@@ -164,16 +166,16 @@ std::shared_ptr<CodeObject> get_or_build(const std::string& source, const std::s
     keytext += '\0';
     for (auto& o : opts) (keytext += o) += '\0';
     keytext += version;
-    std::string key = sha256_hex(keytext.data(), keytext.size());
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_cache.find(key);
+        auto it = g_cache.find(keytext);
         if (it != g_cache.end()) {
             g_mem_hits++;
             *status = HIPMR_OK;
             return it->second;
         }
     }
+    std::string key = sha256_hex(keytext.data(), keytext.size());
     auto co = std::make_shared<CodeObject>();
     co->key = key;
     co->symbol = symbol;
@@ -190,7 +192,7 @@ std::shared_ptr<CodeObject> get_or_build(const std::string& source, const std::s
         write_disk(dir, path, co->image);
     }
     std::lock_guard<std::mutex> lk(g_mu);
-    auto ins = g_cache.emplace(key, co);
+    auto ins = g_cache.emplace(std::move(keytext), co);
     *status = HIPMR_OK;
     return ins.first->second;
 }

@@ -23,6 +23,7 @@ is one fused kernel too.
 
 from __future__ import annotations
 
+import functools
 import hashlib
 import math
 import numbers
@@ -168,6 +169,14 @@ def _name(text):
     return "lazy_" + hashlib.sha256(text.encode()).hexdigest()[:10]
 
 
+@functools.lru_cache(maxsize=1024)
+def _kernel(expr, dtypes, name):
+    """The compiled handle of one rendered expression, kept for the next
+    evaluation of the same tree shape (the library's own cache would find
+    it too, after parsing and rendering the source again)."""
+    return _hm.compile(expr, dtypes, name=name)
+
+
 def elementwise_source(node: LazyArray):
     """(dtypes, statement, leaves) of the fused elementwise kernel."""
     expr, leaves = render(node)
@@ -201,7 +210,7 @@ def evaluate(node: LazyArray, out=None, fused=True, stream=None):
     n = _length(leaves)
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=leaves[0].device)
-    k = _hm.compile(stmt, dtypes, name=_name(stmt))
+    k = _kernel(stmt, dtypes, _name(stmt))
     _hm.elementwise(k, n, [out, *leaves], stream=stream)
     return out
 
@@ -237,7 +246,7 @@ def _reduce(node, combine, neutral, out, stream):
     n = _length(leaves)
     if out is None:
         out = torch.empty((), dtype=torch.float32, device=leaves[0].device)
-    k = _hm.compile(expr, dtypes, name=_name(dtypes + expr))
+    k = _kernel(expr, dtypes, _name(dtypes + expr))
     _hm.reduce(k, None, combine, neutral, n, leaves, out, stream=stream)
     return out
 
