@@ -194,7 +194,8 @@ def bench_dot(torch, hm, workloads, dev, stream, reps=200):
     HBM traffic): a launch-bound call, reported in microseconds.  `async_us`
     is the per-call time of back-to-back calls (HIP events around all of
     them); `synced_us` the median of single calls each followed by a host
-    synchronisation (submission + both kernels + the wait)."""
+    synchronisation (submission + both kernels + the wait); `graph_us` the
+    per-call time of ten calls captured in one HIP graph and replayed."""
     x, y = workloads.dot_1m()
     xd, yd = (torch.from_numpy(a).to(dev) for a in (x, y))
     out = torch.empty((), dtype=torch.float32, device=dev)
@@ -219,9 +220,26 @@ def bench_dot(torch, hm, workloads, dev, stream, reps=200):
         torch.cuda.synchronize()
         synced.append((time.perf_counter() - t0) * 1e6)
     gpu_ms = _time_ms(torch, call, reps, stream)
+    eager = out.clone()
+    # ten calls captured in one HIP graph (on a side stream: the legacy
+    # default stream cannot be captured), replayed: the per-call time with
+    # the host's launch overhead taken away
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = hm.Graph()
+    with graph.capture(side):
+        for _ in range(10):
+            hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], out, workspace_buf=ws, stream=side)
+    out.fill_(float("nan"))
+    torch.cuda.synchronize()
+    graph.launch(side)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, eager))
+    graph_ms = _time_ms(torch, lambda: graph.launch(side), 20, side) / 10
     return {"n": int(x.size), "bytes": 8 * int(x.size), "async_us": round(async_us, 2),
             "synced_us_p50": round(float(np.median(synced)), 2),
             "event_us_p50": round(gpu_ms * 1e3, 2),
+            "graph_us_per_call": round(graph_ms * 1e3, 2), "graph_equals_eager": same,
             "GB/s_async": round(8 * x.size / async_us / 1e3, 1),
             "note": "launch-bound: 8.4 MB is about 1 us of HBM traffic; GB/s is not a roofline claim"}
 

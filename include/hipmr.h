@@ -444,8 +444,11 @@ hipmr_status hipmr_server_create(const hipmr_server_config *cfg, void *workspace
  * packed.  *ticket identifies its completion in hipmr_server_poll. */
 hipmr_status hipmr_server_submit(hipmr_server_t s, const hipmr_sjob *job, uint64_t *ticket);
 
-/* Copies up to cap completions of submitted jobs into done; *ndone receives
- * the count.  Reports a launch failure of the loop as its status. */
+/* Copies up to cap completions of submitted jobs into done, oldest first;
+ * *ndone receives the count.  Reports a launch failure of the loop as its
+ * status.  A job whose batch failed to launch or run completes with E_HIP;
+ * if the loop's thread cannot select the device, every job completes at once
+ * with E_HIP, so no wait is left without an end. */
 hipmr_status hipmr_server_poll(hipmr_server_t s, hipmr_completion *done, int32_t cap,
                                int32_t *ndone);
 

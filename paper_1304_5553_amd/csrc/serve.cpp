@@ -713,8 +713,11 @@ struct hipmr_server {
             if (s.jobs.empty()) break;       // budget full: wait for completions
             hipmr_status st = launch_batch(s);
             if (st != HIPMR_OK) {
-                worker_status = st;
-                worker_error = last_error();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    worker_status = st;
+                    worker_error = last_error();
+                }
                 for (const Pending& p : s.jobs) {
                     admitted -= p.bytes;
                     complete(p, st, (int32_t)s.jobs.size(), now_ns(), now_ns());
@@ -726,10 +729,43 @@ struct hipmr_server {
         return progressed;
     }
 
+    // The loop cannot use the device: every job, submitted or scheduled, is
+    // completed at once with E_HIP (nothing waits for a result that never
+    // comes) until the server is destroyed.
+    void fail_every_job() {
+        while (true) {
+            std::vector<Pending> failed;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                while (!incoming.empty()) {
+                    failed.push_back(incoming.front());
+                    incoming.pop_front();
+                }
+                while (sched && sched_next < sched_n) {
+                    const hipmr_sjob& j = sched[sched_next];
+                    failed.push_back(Pending{j, (1ull << 62) + (uint64_t)sched_next, sched_t0 + j.arrival_ns,
+                                             job_bytes(j), 0, 0});
+                    ++sched_next;
+                }
+                if (failed.empty()) {
+                    if (stop.load()) return;
+                    cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                    continue;
+                }
+            }
+            const int64_t t = now_ns();
+            for (const Pending& p : failed) complete(p, HIPMR_E_HIP, 0, t, t);
+        }
+    }
+
     void loop() {
         if (hipSetDevice(device) != hipSuccess) {
-            worker_status = HIPMR_E_HIP;
-            worker_error = "hipSetDevice failed in the serving thread";
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                worker_status = HIPMR_E_HIP;
+                worker_error = "hipSetDevice failed in the serving thread";
+            }
+            fail_every_job();
             return;
         }
         while (true) {
@@ -863,11 +899,9 @@ hipmr_status hipmr_server_poll(hipmr_server_t s, hipmr_completion* done, int32_t
     clear_error();
     if (!s || !ndone || (cap > 0 && !done)) return fail(HIPMR_E_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    int32_t k = 0;
-    while (k < cap && !s->finished.empty()) {
-        done[k++] = s->finished.front();
-        s->finished.erase(s->finished.begin());
-    }
+    const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(cap, 0), s->finished.size());
+    std::copy(s->finished.begin(), s->finished.begin() + k, done);
+    s->finished.erase(s->finished.begin(), s->finished.begin() + k);
     *ndone = k;
     if (s->worker_status != HIPMR_OK) return fail(s->worker_status, s->worker_error);
     return HIPMR_OK;
@@ -939,6 +973,7 @@ hipmr_status hipmr_server_run_schedule(hipmr_server_t s, const hipmr_sjob* jobs,
     }
     for (int32_t k = 0; k < njobs; ++k)
         if (!ok[k]) done[k].ticket = (uint64_t)k;
+    std::lock_guard<std::mutex> lk(s->mu);
     if (s->worker_status != HIPMR_OK) return fail(s->worker_status, s->worker_error);
     return HIPMR_OK;
 }
