@@ -86,6 +86,7 @@ def cpu_baseline(x, y, k, sample):
     m = min(sample, x.size)
     xs, ys, ks = x[:m], y[:m], k[:m]
     zero = np.zeros(1, np.float32)
+    c0 = time.process_time()
     t0 = time.perf_counter()
     oracle.elementwise(workloads.E1[0], workloads.E1[1], m, [zero, xs, ys])
     oracle.elementwise(workloads.E2[0], workloads.E2[1], m, [zero, xs, ys])
@@ -93,9 +94,10 @@ def cpu_baseline(x, y, k, sample):
         oracle.reduce(sig, mp, comb, neu, m, [ks])
     oracle.reduce(workloads.R_MAX[0], workloads.R_MAX[1], "max(a,b)", "-INFINITY", m, [xs])
     dt = time.perf_counter() - t0
+    busy = (time.process_time() - c0) / dt     # CPU seconds per second: threads in use
     nbytes = m * (12 + 12 + 4 + 4 + 4)
-    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": max(1, round(busy)),
+            "cpu_s_per_s": round(busy, 2), "kind": "oracle",
             "sample": f"first {m} elements of each of E1, E2, R1, R2, R3 "
                       f"({nbytes / 1e6:.0f} MB algorithmic) in {dt:.1f} s"}
 
