@@ -184,6 +184,9 @@ def _check(status):
 def _stream_ptr(stream):
     if stream is None:
         import torch
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:      # the current stream's handle without a Stream object
+            return raw(torch.cuda.current_device())
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream
@@ -269,6 +272,7 @@ class Kernel:
         # arrays that must hold n elements (accessed at i or i +/- E)
         self._sized = [k for k, a in enumerate(self.args)
                        if a.pointer and a.access & (ACCESS_INDEX | ACCESS_SHIFTED)]
+        self._tls = threading.local()     # per-thread argument buffers (see marshal)
 
     @property
     def handle(self):
@@ -292,14 +296,20 @@ class Kernel:
                                    f"fewer than n = {n}")
 
     def marshal(self, args):
-        """(keep-alive storage, ctypes array of pointers) for the C ABI's args:
-        every value sits in its own 8-byte slot of one buffer (a device
-        pointer, or the scalar's bytes in its C type), and args[k] points at
-        slot k."""
+        """(storage, ctypes array of pointers) for the C ABI's args: every
+        value sits in its own 8-byte slot of one buffer (a device pointer, or
+        the scalar's bytes in its C type), and args[k] points at slot k.  The
+        library copies the values during the call, so each thread reuses one
+        pair of buffers per handle, rewritten by its next call."""
         if len(args) != len(self.args):
             raise InvalidError(f"expected {len(self.args)} arguments, got {len(args)}")
-        nargs = max(1, len(args))
-        store = (ctypes.c_uint64 * nargs)()
+        bufs = getattr(self._tls, "bufs", None)
+        if bufs is None:
+            nargs = max(1, len(args))
+            store = (ctypes.c_uint64 * nargs)()
+            base = ctypes.addressof(store)
+            bufs = self._tls.bufs = (store, (ctypes.c_void_p * nargs)(*range(base, base + 8 * nargs, 8)))
+        store, ptrs = bufs
         for k, (decl, val) in enumerate(zip(self.args, args)):
             if decl.pointer:
                 store[k] = val if isinstance(val, int) else (0 if val is None else val.data_ptr())
@@ -312,8 +322,6 @@ class Kernel:
                 store[k] = int(val) & _INT_MASK[decl.dtype]
             else:                                      # float / double, as C converts them
                 struct.pack_into(_PACK[decl.dtype], store, 8 * k, _CTYPE[decl.dtype](val).value)
-        base = ctypes.addressof(store)
-        ptrs = (ctypes.c_void_p * nargs)(*range(base, base + 8 * nargs, 8))
         return store, ptrs
 
     def last_symbols(self):

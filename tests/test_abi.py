@@ -152,6 +152,29 @@ def test_marshal_holds_each_value_in_its_c_type():
         k.marshal(vals[:-1])
 
 
+def test_marshal_reuses_one_buffer_per_thread():
+    # the library copies argument values during the call, so a handle keeps
+    # one pair of buffers per thread; the next call rewrites every slot
+    import threading
+
+    import torch
+    k = hm.compile("z[i] = a * x[i] + b", "float *z, float a, const float *x, long b")
+    z, x = torch.zeros(4), torch.ones(4)
+    s1, p1 = k.marshal([z, 2.5, x, -7])
+    addr = ctypes.addressof(s1)
+    s2, p2 = k.marshal([x, -0.5, z, 2 ** 40])
+    assert ctypes.addressof(s2) == addr and p2[0] == addr
+    want = [ctypes.c_void_p(x.data_ptr()), ctypes.c_float(-0.5), ctypes.c_void_p(z.data_ptr()),
+            ctypes.c_int64(2 ** 40)]
+    for i, w in enumerate(want):
+        assert ctypes.string_at(p2[i], ctypes.sizeof(w)) == bytes(w), i
+    other = []
+    t = threading.Thread(target=lambda: other.append(ctypes.addressof(k.marshal([z, 1.0, x, 1])[0])))
+    t.start()
+    t.join()
+    assert other and other[0] != addr
+
+
 def test_generated_source_shape():
     k = hm.compile("z[i] = 2.5f*x[i] - 0.5f*y[i]", "float *z, const float *x, const float *y",
                    name="lin")

@@ -594,3 +594,24 @@ def test_shifted_reads_at_timed_sizes(dev, flags):
     assert out.item() == float(want), (out.item(), want)
     del xd
     torch.cuda.empty_cache()
+
+
+def test_default_stream_is_torchs_current_stream(dev):
+    # calls without a stream launch on torch's current stream, read as a raw
+    # handle: the same stream inside and outside a stream context, and the
+    # work lands there (ordered with torch's own work on that stream)
+    from paper_1304_5553_amd import hipmr as binding
+    assert binding._stream_ptr(None) == torch.cuda.current_stream().cuda_stream
+    side = torch.cuda.Stream()
+    k = hm.compile(E1_STMT, E1_SIG, name="e1_lincomb")
+    n = 1 << 20
+    x = torch.ones(n, device=dev)
+    y = torch.full((n,), 2.0, device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        assert binding._stream_ptr(None) == side.cuda_stream != torch.cuda.default_stream().cuda_stream
+        z = torch.empty(n, device=dev)
+        hm.elementwise(k, n, [z, x, y])
+        w = z * 2.0                                  # torch's work on the same stream
+    side.synchronize()
+    assert bool(torch.all(w == 3.0))
