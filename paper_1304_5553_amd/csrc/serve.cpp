@@ -525,6 +525,18 @@ struct hipmr_server {
     std::string worker_error;
     std::thread worker;
 
+    // Frees what hipmr_server_create allocated, also when it failed part
+    // way; runs after the loop's thread has ended (or was never started).
+    ~hipmr_server() {
+        for (auto& sl : slots) {
+            if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.host_desc) (void)hipHostFree(sl.host_desc);
+            if (sl.flags) (void)hipHostFree(sl.flags);
+        }
+        if (module) (void)hipModuleUnload(module);
+    }
+
     void complete(const Pending& p, int32_t status, int32_t batch_jobs, int64_t launch, int64_t done) {
         hipmr_completion c{};
         c.ticket = p.ticket;
@@ -983,14 +995,7 @@ void hipmr_server_destroy(hipmr_server_t s) {
     s->stop = true;
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    for (auto& sl : s->slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        if (sl.host_desc) (void)hipHostFree(sl.host_desc);
-        if (sl.flags) (void)hipHostFree(sl.flags);
-    }
-    if (s->module) (void)hipModuleUnload(s->module);
-    delete s;
+    delete s;   // the destructor frees the streams, pinned buffers and module
 }
 
 }  // extern "C"

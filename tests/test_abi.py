@@ -270,3 +270,31 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(hm.hipmr, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         hm.compile("z[i] = x[i]", "float *z, const float *x")
+
+
+def test_server_config_validation_without_a_gpu():
+    # the serving entry points check their arguments before any HIP call:
+    # bad configurations, a missing or short workspace and NULL servers
+    B = hm.hipmr
+    L = B.lib()
+    base = B.ServerConfig()
+    need = L.hipmr_server_workspace_bytes(ctypes.byref(base))
+    two = B.ServerConfig(nstreams=2)
+    assert need > 0 and L.hipmr_server_workspace_bytes(ctypes.byref(two)) * 2 == need
+    buf = ctypes.create_string_buffer(need)
+    out = ctypes.c_void_p()
+    for bad in (dict(nstreams=17), dict(nstreams=-1), dict(max_batch_jobs=4097),
+                dict(max_batch_tiles=-1), dict(batch_backlog=-1),
+                dict(max_batch_bytes=1 << 20, solo_bytes=2 << 20)):
+        st = L.hipmr_server_create(ctypes.byref(B.ServerConfig(**bad)), buf, need, ctypes.byref(out))
+        assert st == -1 and not out.value, bad
+    assert L.hipmr_server_create(ctypes.byref(base), None, need, ctypes.byref(out)) == -8
+    assert L.hipmr_server_create(ctypes.byref(base), buf, need - 1, ctypes.byref(out)) == -8
+    assert L.hipmr_server_create(ctypes.byref(base), buf, need, None) == -1
+    nd = ctypes.c_int32()
+    t = ctypes.c_uint64()
+    assert L.hipmr_server_poll(None, None, 0, ctypes.byref(nd)) == -1
+    assert L.hipmr_server_submit(None, None, ctypes.byref(t)) == -1
+    assert L.hipmr_server_wait_idle(None) == -1
+    assert L.hipmr_server_run_schedule(None, None, 0, None) == -1
+    L.hipmr_server_destroy(None)
