@@ -515,9 +515,10 @@ hipmr_status hipmr_get_kernel_source(hipmr_handle h, int32_t kind, const char *c
 hipmr_status hipmr_get_last_symbols(hipmr_handle h, char *buf, size_t cap, size_t *len);
 
 /* Compile-cache counters (process-wide).  Section "Core Method": a source
- * already compiled is found in memory or in the on-disk cache
- * ($HIPMR_CACHE_DIR, default $XDG_CACHE_HOME/hipmr or ~/.cache/hipmr) instead
- * of recompiling. */
+ * already compiled is found in memory (looked up by the source text) or in
+ * the on-disk cache (a file named by the SHA-256 of the source, compiler
+ * options and hipRTC version, under $HIPMR_CACHE_DIR, default
+ * $XDG_CACHE_HOME/hipmr or ~/.cache/hipmr) instead of recompiling. */
 typedef struct hipmr_cache_stats {
     uint64_t memory_hits;
     uint64_t disk_hits;
@@ -528,12 +529,14 @@ typedef struct hipmr_cache_stats {
 
 hipmr_status hipmr_get_cache_stats(hipmr_cache_stats *out);
 
-/* Forgets the in-memory cache of code objects (handles stay valid and reload
- * from the disk cache or recompile on next use).  For tests of the disk cache. */
+/* Forgets the in-memory cache of code objects.  Existing handles stay valid
+ * and keep the kernels they have built; new handles, and kernels a handle has
+ * not built yet, come from the disk cache or are recompiled.  For tests and
+ * measurements of the disk cache. */
 void hipmr_cache_drop_memory(void);
 
-/* Hex SHA-256 (FIPS 180-4) of a byte string, the function behind cache keys.
- * out must hold 65 bytes. */
+/* Hex SHA-256 (FIPS 180-4) of a byte string, the function behind the disk
+ * cache's file names and the hash in kernel symbols.  out must hold 65 bytes. */
 hipmr_status hipmr_sha256_hex(const void *data, size_t len, char *out);
 
 /* Size in bytes of a dtype code, 0 if unknown. */
