@@ -272,6 +272,17 @@ def test_missing_library_fails_loudly(monkeypatch):
         hm.compile("z[i] = x[i]", "float *z, const float *x")
 
 
+def test_product_code_never_uses_the_oracle():
+    # the oracle is test infrastructure: the package (Python and native
+    # sources) neither imports nor names it, and shares none of its files
+    import pathlib
+    pkg = pathlib.Path(hm.__file__).resolve().parent
+    for f in list(pkg.rglob("*.py")) + list(pkg.rglob("*.cpp")) + list(pkg.rglob("*.h")):
+        text = f.read_text()
+        assert "import oracle" not in text and "from oracle" not in text, f
+        assert "oracle/" not in text, f
+
+
 def test_server_config_validation_without_a_gpu():
     # the serving entry points check their arguments before any HIP call:
     # bad configurations, a missing or short workspace and NULL servers
