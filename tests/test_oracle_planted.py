@@ -1,0 +1,90 @@
+"""Planted mistakes, on the CPU: each patches one plausible bug into the
+oracle (a dropped term, C division taken as floor division, a transposed
+operand, a missing rounding allowance, a lost sign bit, a naive float sum)
+and checks that the pins catch it.  The GPU library is never involved."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.interp as interp
+import test_oracle_pins as pins
+
+REDUCE_MOD = sys.modules["oracle.reduce"]
+
+
+def caught(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_dropped_last_term(monkeypatch):
+    real = oracle.reduce
+
+    def planted(sig, mp, comb, neu, n, args, *a, **kw):
+        return real(sig, mp, comb, neu, max(n - 1, 0), args, *a, **kw)
+    monkeypatch.setattr(oracle, "reduce", planted)
+    assert caught(pins.test_sum_of_index_closed_form)
+    assert caught(pins.test_listing3b_dot_of_arange)
+    assert caught(pins.test_count_mod7_closed_form, 46)       # element 45 counts (45 % 7 == 3)
+
+
+def test_floor_division_instead_of_c_truncation(monkeypatch):
+    real = interp.Interp._int_arith
+
+    def planted(self, op, a, b, t, u, active):
+        if op in ("/", "%"):
+            ys = np.where(b.v == 0, 1, b.v)
+            return self._int_result(t, a.v // ys if op == "/" else a.v % ys, u, active)
+        return real(self, op, a, b, t, u, active)
+    monkeypatch.setattr(interp.Interp, "_int_arith", planted)
+    assert caught(pins.test_integer_c_semantics_brute_force)
+
+
+def test_transposed_subtraction(monkeypatch):
+    real = interp.Interp._float_arith
+
+    def planted(self, op, a, b, t, u, active):
+        if op == "-":
+            a, b = b, a
+        return real(self, op, a, b, t, u, active)
+    monkeypatch.setattr(interp.Interp, "_float_arith", planted)
+    stmt, f32 = "z[i] = 2.5f*x[i] - 0.5f*y[i]", lambda x, y: np.float32(2.5) * x - np.float32(0.5) * y
+    assert caught(pins.test_error_bound_contains_float32_evaluations, stmt, f32)
+
+
+def test_missing_rounding_allowance(monkeypatch):
+    monkeypatch.setattr(interp, "UNIT", {k: 0.0 for k in interp.UNIT})
+    stmt, f32 = "z[i] = sqrtf(x[i]*x[i] + y[i]*y[i])", lambda x, y: np.sqrt(x * x + y * y)
+    assert caught(pins.test_error_bound_contains_float32_evaluations, stmt, f32)
+
+
+def test_lost_sign_bit_in_a_decoder(monkeypatch):
+    pytest.importorskip("torch")
+    real = oracle.decode_bf16
+    monkeypatch.setattr(oracle, "decode_bf16", lambda bits: np.abs(real(bits)))
+    assert caught(pins.test_decoders_match_torch_for_every_code)
+
+
+def test_naive_float_sum(monkeypatch):
+    class NaiveMath:
+        sqrt = staticmethod(math.sqrt)
+        isnan = staticmethod(math.isnan)
+        isinf = staticmethod(math.isinf)
+        inf = math.inf
+
+        @staticmethod
+        def fsum(values):
+            s = 0.0
+            for v in values:
+                s += v
+            return s
+    monkeypatch.setattr(REDUCE_MOD, "math", NaiveMath)
+    assert any(caught(pins.test_float_sum_is_the_correctly_rounded_exact_sum, seed)
+               for seed in range(6))
