@@ -88,3 +88,45 @@ def test_naive_float_sum(monkeypatch):
     monkeypatch.setattr(REDUCE_MOD, "math", NaiveMath)
     assert any(caught(pins.test_float_sum_is_the_correctly_rounded_exact_sum, seed)
                for seed in range(6))
+
+
+def test_exclusive_scan_not_shifted(monkeypatch):
+    import test_oracle_scan_pins as scan_pins
+    real = oracle.scan
+    monkeypatch.setattr(oracle, "scan", lambda *a, exclusive=False, **kw: real(*a, **kw))
+    assert caught(scan_pins.test_inclusive_and_exclusive_sum_of_index_closed_form)
+
+
+def test_periodic_stencil_boundary(monkeypatch):
+    # the five-point operator with wrap-around neighbours instead of the
+    # Dirichlet boundary
+    import test_oracle_cg_pins as cg_pins
+
+    def planted(p, nx):
+        g = np.asarray(p, np.float64).reshape(-1, nx)
+        return (4 * g - np.roll(g, 1, 0) - np.roll(g, -1, 0) - np.roll(g, 1, 1)
+                - np.roll(g, -1, 1)).reshape(-1)
+    monkeypatch.setattr(oracle, "laplace5", planted)
+    assert caught(cg_pins.test_operator_is_scipys_sparse_laplacian, 7, 5)
+
+
+def test_cg_with_a_scaled_operator(monkeypatch):
+    # a dropped factor inside the solver's operator (2A instead of A)
+    import test_oracle_cg_pins as cg_pins
+    mod = sys.modules["oracle.cg"]
+    real = mod.laplace5
+    monkeypatch.setattr(mod, "laplace5", lambda p, nx: 2.0 * real(p, nx))
+    assert caught(cg_pins.test_cg_reaches_the_direct_solution)
+
+
+def test_conj_that_does_not_conjugate(monkeypatch):
+    import test_oracle_complex_pins as complex_pins
+    real = interp.Interp._complex_call
+
+    def planted(self, f, args, active):
+        if f == "conj":
+            return self.convert(args[0], interp.CFLOAT, active)
+        return real(self, f, args, active)
+    monkeypatch.setattr(interp.Interp, "_complex_call", planted)
+    assert caught(complex_pins.test_conjugated_dot_is_the_exact_sum)
+    assert caught(complex_pins.test_gaussian_integer_products_are_exact)
