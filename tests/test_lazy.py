@@ -117,3 +117,18 @@ def test_same_tree_same_kernel():
     k1 = hm.compile(a[1], a[0], name=lz._name(a[1]))
     k2 = hm.compile(b[1], b[0], name=lz._name(b[1]))
     assert k1.source(0) == k2.source(0)
+
+
+def test_repeated_evaluation_reuses_the_compiled_handle():
+    # a tree of the same shape over other arrays renders the same statement,
+    # so its evaluation reuses the handle compiled for the first one
+    x, y, w = (lz.lazy(t) for t in leaves(10, 2))
+    p, q, r = (lz.lazy(t) for t in leaves(20, 3))
+    a = lz.elementwise_source(2.5 * x * y - w)
+    b = lz.elementwise_source(2.5 * p * q - r)
+    assert a[:2] == b[:2]
+    k1 = lz._kernel(a[1], a[0], lz._name(a[1]))
+    k2 = lz._kernel(b[1], b[0], lz._name(b[1]))
+    assert k1 is k2
+    c = lz.elementwise_source(2.5 * x * y + w)
+    assert lz._kernel(c[1], c[0], lz._name(c[1])) is not k1
