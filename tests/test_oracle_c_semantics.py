@@ -74,3 +74,35 @@ def test_uint32_operators_follow_c(op, a, b):
             run("unsigned", op, a, b, np.uint32)
     else:
         assert run("unsigned", op, a, b, np.uint32) == want
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.one_of(I32, st.integers(-(2 ** 62), 2 ** 62)))
+def test_integer_to_float_bound_holds_the_rounded_value(v):
+    # (float) of an int / long: the oracle keeps the exact value with an
+    # allowance of one float32 rounding, which must contain numpy's
+    # round-to-nearest-even conversion and be no wider than 2^-24 |v|
+    ctype, np_t = ("int", np.int32) if -(2 ** 31) <= v < 2 ** 31 else ("long", np.int64)
+    k = np.array([v], np_t)
+    out = np.zeros(1, np.float32)
+    o = oracle.elementwise(f"const {ctype} *k, float *o", "o[i] = (float)k[i]", 1, [k, out])["o"]
+    exact, e = o.v.tolist()[0], float(o.e[0])
+    assert exact == float(v) or abs(exact - v) <= abs(v) * 2.0 ** -53
+    # (plus, above 2^53, the float64 representation error of the value itself)
+    assert abs(float(np.float32(v)) - exact) <= e <= (2.0 ** -24 + 2.0 ** -52) * abs(v) * (1 + 1e-9) + 2.0 ** -126
+
+
+@settings(max_examples=300, deadline=None)
+@given(st.floats(-3e9, 3e9, width=32, allow_nan=False))
+def test_float_to_int_truncates_or_raises(f):
+    # (int) of a float truncates toward zero; outside the int range C leaves
+    # the conversion undefined and the oracle raises
+    x = np.array([f], np.float32)
+    out = np.zeros(1, np.int32)
+    t = int(np.trunc(np.float64(x[0])))
+    if -(2 ** 31) <= t < 2 ** 31:
+        o = oracle.elementwise("const float *x, int *o", "o[i] = (int)x[i]", 1, [x, out])["o"]
+        assert o.v.tolist()[0] == t
+    else:
+        with pytest.raises(OracleError):
+            oracle.elementwise("const float *x, int *o", "o[i] = (int)x[i]", 1, [x, out])
