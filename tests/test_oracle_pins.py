@@ -387,3 +387,26 @@ def test_signature_parser():
         oracle.parse_signature("quux *z")
     with pytest.raises(ValueError):
         oracle.parse_signature("float *z, int z")
+
+
+# ------------------------------------------------------------ library cross-checks
+def test_library_cross_checks_on_the_small_dot_inputs():
+    # the small dot's inputs (2^20 float32 values, seed 0): the oracle's dot
+    # is Python's correctly rounded fsum of the exact float64 products; its
+    # max is numpy's; its sum and norm agree with torch's float64 reductions
+    # to within float64 rounding
+    import workloads
+    torch = pytest.importorskip("torch")
+    x, y = workloads.dot_1m()
+    n = x.size
+    r = oracle.reduce("float: const float *x, const float *y", "x[i]*y[i]", "a+b", "0", n, [x, y])
+    assert r.value == math.fsum((x.astype(np.float64) * y.astype(np.float64)).tolist())
+    m = oracle.reduce("float: const float *x", "x[i]", "max(a,b)", "-INFINITY", n, [x])
+    assert m.value == float(np.max(x))
+    s = oracle.reduce("double: const float *x", "x[i]", "a+b", "0", n, [x]).value
+    t = torch.from_numpy(x).double()
+    assert abs(s - float(torch.sum(t))) <= 1e-12 * float(torch.sum(t.abs()))
+    # (torch's float64 reductions are not correctly rounded: allow their
+    # summation error, far below what a dropped or doubled term would move)
+    nrm = oracle.norm2(x)
+    assert abs(nrm - float(torch.linalg.vector_norm(t))) <= 1e-12 * nrm
