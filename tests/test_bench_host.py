@@ -40,3 +40,22 @@ def test_counter_traffic_by_symbol():
     t = bench.counter_traffic(sym)
     assert t is not None and abs(t - 12 * 2 ** 28) <= 0.01 * 12 * 2 ** 28
     assert bench.counter_traffic("e1_lincomb_ew_00000000") is None
+
+
+def test_profile_commands_are_valid_bench_invocations(monkeypatch):
+    # every committed rocprofv3 summary names the command that made it; the
+    # program after "--" is this benchmark, with options it still accepts
+    import glob
+    import shlex
+    cmds = []
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if "rocprofv3" in line and " -- " in line:
+                cmds.append((os.path.basename(path), line.split(" -- ", 1)[1].strip()))
+    assert len(cmds) >= 10
+    for name, cmd in cmds:
+        argv = shlex.split(cmd)
+        assert argv[:2] == ["python", "bench.py"], (name, cmd)
+        monkeypatch.setattr(sys, "argv", argv[1:])
+        args = bench.parse()
+        assert args.gpus == 1, (name, cmd)
