@@ -118,7 +118,8 @@ def _time_ms(torch, fn, reps, stream):
 
 
 def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
-    """Rows a1-a4 on the host: the cost of compile(expr, dtypes) when hipRTC
+    """The host side of the path (front end, code generation, compile cache,
+    launch): the cost of compile(expr, dtypes) when hipRTC
     runs (cold), when the code object comes from the disk cache (after the
     in-memory cache is dropped) and when it is in memory (front end, code
     generation and the SHA-256 key only), for E1 and for R2's two reduce
