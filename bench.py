@@ -122,7 +122,8 @@ def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
     launch): the cost of compile(expr, dtypes) when hipRTC
     runs (cold), when the code object comes from the disk cache (after the
     in-memory cache is dropped) and when it is in memory (front end, code
-    generation and the SHA-256 key only), for E1 and for R2's two reduce
+    generation with the symbol's SHA-256, and the lookup), for E1 and for
+    R2's two reduce
     kernels; then the host time of one elementwise call (argument marshalling
     and the enqueue) and the GPU time per launch of a 4096-element E1, back to
     back.  Each cold source is new (its own kernel name) and the disk cache is
