@@ -115,6 +115,10 @@ typedef struct hipmr_launch_config {
 #define HIPMR_CFG_TEMPORAL_STORES 16  /* streaming loads, ordinary stores                    */
 #define HIPMR_CFG_SEG_GLOBAL      32  /* segmented: read the tile table from global memory
                                          even when it would fit in LDS                       */
+#define HIPMR_CFG_TUNED           64  /* hipmr_reduce_ex / hipmr_reduce_segmented: use the
+                                         geometry the autotuner stored for this handle,
+                                         operation and size class, when there is one (else
+                                         the other fields); never applied without the flag */
 /* Streaming stores apply to chunks of at most 16 bytes per lane; a wider
  * chunk (e.g. four 64-bit results) leaves in several instructions that each
  * fill half lines, and is stored temporally so that the L2 merges them. */
@@ -300,26 +304,61 @@ size_t hipmr_segmented_workspace_bytes(hipmr_handle h, int32_t nseg, int64_t tot
  * the map indexing the concatenated arrays with the global index i (and n =
  * total_n).  Batching extension of the map-reduce (section "Map-Reduce").
  *   d_offsets: device int64 array of nseg + 1 non-decreasing offsets into
- *              [0, total_n]; values outside are clamped, a decreasing pair gives
- *              an empty segment (never an out-of-bounds access).
+ *              [0, total_n]; values outside are clamped and a decreasing pair
+ *              gives an empty segment.  Offsets that are not non-decreasing
+ *              (overlapping segments) may describe more tiles than the
+ *              workspace holds: the planner then caps the tile table at the
+ *              workspace's capacity, no kernel reads or writes past it, and
+ *              the results of the segments whose tiles fall past the cap are
+ *              unspecified (never an out-of-bounds access, whatever the
+ *              offsets, including offsets changed between graph replays).
  *   d_out:     device array of nseg elements of the result type.
  *   workspace: at least hipmr_segmented_workspace_bytes(h, nseg, total_n).
+ *   cfg:       NULL (the default geometry) or a geometry; with HIPMR_CFG_TUNED
+ *              the one hipmr_autotune_segmented stored for this handle,
+ *              combine_op, neutral and size class, if any.
  * Three launches on stream: a one-block planner turns the offsets into tiles
  * (tile 0 of a segment holds its unaligned head and up to T body elements,
  * later tiles T elements, T = 64 * vec * items_per_thread); a persistent
  * kernel whose waves each reduce one tile at a time into a tile partial; one
  * wave per segment folding its tiles in order.  A segment's result depends
  * only on its own bounds and the geometry, so it is bitwise the same whatever
- * the other segments are.  With cfg == NULL the geometry stored by
- * hipmr_autotune_segmented for this handle, combine_op, neutral and size class
- * is used, else the default.  Everything stays on the device, so the sequence
+ * the other segments are.  Everything stays on the device, so the sequence
  * can be captured once and replayed with new offset values.
- * Errors: as hipmr_reduce; E_WORKSPACE for a short workspace. */
+ * Errors: as hipmr_reduce; E_WORKSPACE for a short workspace; E_UNSUPPORTED
+ * when nseg + total_n / 64 + 1 (the tile capacity) exceeds 2^31 - 1. */
 hipmr_status hipmr_reduce_segmented(hipmr_handle h, const char *combine_op, const char *neutral,
                                     int32_t nseg, const int64_t *d_offsets, int64_t total_n,
                                     void *const *args, void *d_out, void *workspace,
                                     size_t workspace_bytes, const hipmr_launch_config *cfg,
                                     void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * segmented map-reduce as hipmr_reduce_segmented, with the same kernels and
+ * results, but its tile table and tile partials live in a static device array
+ * of the library (HIPMR_NOALLOC_SCRATCH_BYTES per device, held from the first
+ * call on a device until the process ends) instead of a caller workspace.
+ *   Arguments as hipmr_reduce_segmented, without the workspace.
+ *   The call allocates nothing: it neither builds nor loads kernels, so run
+ *   hipmr_reduce_segmented once on this device with the same handle,
+ *   combine_op, neutral, geometry and argument alignment first (E_INVALID
+ *   otherwise).  Its first call on a device looks up the array's device
+ *   address there.
+ *   Every call on one device shares that device's array: calls that overlap
+ *   on one device (two streams, two threads) race and give wrong results.
+ *   Nothing in the array needs to start at zero (every entry read is written
+ *   first by the same call).
+ * Errors: as hipmr_reduce_segmented; E_WORKSPACE when the segments need more
+ * than HIPMR_NOALLOC_SCRATCH_BYTES (hipmr_segmented_workspace_bytes(h, nseg,
+ * total_n) bytes: e.g. 4096 segments over about 2^27 float elements). */
+#define HIPMR_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+size_t hipmr_noalloc_scratch_bytes(void);
+hipmr_status hipmr_reduce_segmented_noalloc(hipmr_handle h, const char *combine_op,
+                                            const char *neutral, int32_t nseg,
+                                            const int64_t *d_offsets, int64_t total_n,
+                                            void *const *args, void *d_out,
+                                            const hipmr_launch_config *cfg, void *stream);
 
 /* Autotuner (section "Code Generation", "Automated Tuning"; and the future-work
  * note on compiling a search's variants on all CPU cores): generates the
@@ -328,7 +367,9 @@ hipmr_status hipmr_reduce_segmented(hipmr_handle h, const char *combine_op, cons
  * the same hipRTC path, times each reps times on the caller's data with HIP
  * events (median), stores the fastest for this handle, operation and size
  * class in memory and in $HIPMR_CACHE_DIR, and returns it in *best.  Runs
- * the operation (1 + reps) times per candidate, overwriting d_out / out. */
+ * the operation (1 + reps) times per candidate, overwriting d_out / out.
+ * A stored geometry is used only by calls that pass HIPMR_CFG_TUNED; a
+ * stored file that does not resolve to a valid geometry is ignored. */
 hipmr_status hipmr_autotune_segmented(hipmr_handle h, const char *combine_op, const char *neutral,
                                       int32_t nseg, const int64_t *d_offsets, int64_t total_n,
                                       void *const *args, void *d_out, void *workspace,

@@ -19,8 +19,43 @@ commutative; the oracle computes the order-free value wherever one exists:
   complex sums the same, for the real and imaginary parts separately;
 * max / min of floating values: IEEE 754-2019 ``maximum`` / ``minimum``
   (a NaN anywhere gives NaN, -0 orders below +0); of integers: exact;
-* any other reduce expression: a left-to-right fold evaluated with C
-  semantics on the result type (pure Python; small n only).
+* any other reduce expression: a left-to-right fold with C semantics on
+  the result type (pure Python; small n only).  Integer results are exact.
+  For floating results the fold is evaluated in float64 (the ideal value;
+  for an associative and commutative reduce expression the exact fold does
+  not depend on the order) and comes with an order-free error model, below.
+
+Error model of a floating fold under a generic reduce expression.  The
+device folds in the result type along a tree whose shape the paper leaves
+open.  At every step of the left-to-right fold the oracle evaluates the
+reduce expression again, vectorised over all steps, with the interpreter's
+running error bounds:
+
+* r_k, the bound on one evaluation of the expression in the result type with
+  exact operands a_k, b_k (one rounding per operation);
+* the sensitivity to an error in either operand, which must not exceed 1
+  (a non-expansive expression: sums, maxima, selections);
+* |f(a, b)| <= |a| + |b| (magnitudes grow at most like a sum);
+* f(neutral, b) = b (the neutral element is an identity, as the paper's
+  footnote requires).
+
+A step that violates one of them raises ``OracleError``: for such an
+expression (a product, say) this model gives no order-free bound.  Under
+them, in any fold tree, the error at the root is at most the sum of the
+r's of its nodes plus the map values' own errors, and since every node's
+operands are bounded by the sum of |m| over its leaves,
+
+    |device - value| <= rounds * u * D * sum |m_i| + sum e_i + slack,
+
+where u is the unit roundoff of the result type, D the depth of the tree
+(the most combinations on any one map value's path), ``rounds`` the
+largest r_k / (u (|a_k| + |b_k|)) over the steps (1 for ``(a)+(b)``, 2 for
+``a+b+0.0f`` under the interpreter's one-rounding-per-operation rule, 0 for
+a selection such as ``fmaxf(a,b)``) and ``slack`` an absolute allowance for
+steps whose operands are below 2**-80, where r_k is dominated by the
+absolute underflow term.  With rounds = 0 and exact map values the fold
+selects one of its operands at every step, so every order gives the same
+value: the result is then exact.
 
 Canonical reduce spellings (after removing blanks): ``a+b``, ``b+a`` and
 ``sum`` mean the sum; ``max(a,b)``, ``max(b,a)`` and ``max`` the maximum;
@@ -36,7 +71,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .api import map_chunks
-from .ctype import CFLOAT, FLOAT_TYPES, INT, INT_RANGE, LONG, STORAGE_VT, UINT, parse_signature
+from .ctype import CFLOAT, FLOAT_TYPES, INT, INT_RANGE, LONG, STORAGE_VT, UINT, UNIT, parse_signature
 from .interp import Interp, OracleError
 from .parser import parse_expression
 
@@ -61,6 +96,9 @@ class ReduceResult:
     err_sum: float       # sum of map-value error bounds (sums) / their max (max, min)
     unsure: int          # lanes whose map value may legitimately differ on the GPU
     exact: bool          # whether the GPU result must match bit for bit
+    rounds: float = 1.0  # roundings of the result type per combination, per unit
+                         # operand magnitude (floating folds; 1 for the canonical sum)
+    abs_slack: float = 0.0   # absolute allowance for steps with operands below 2**-80
 
 
 def eval_neutral(result_storage: str, neutral: str):
@@ -158,20 +196,98 @@ def reduce(dtypes, map_expr, combine, neutral, n, args) -> ReduceResult:
     # generic reduce expression: left-to-right fold, C semantics
     if n > GENERIC_FOLD_LIMIT:
         raise OracleError("generic folds are evaluated for small n only")
-    expr = parse_expression(combine)
-    storage = sig.result
-    acc = neutral_val.v[0]
-    one = np.ones(1, bool)
+    vals, errs = [], []
     for _, val in chunks:
         unsure += int(np.count_nonzero(val.u))
-        for x in val.v.tolist():
-            it = Interp({}, {}, np.zeros(1, np.int64), 1)
-            it.locals["a"] = (storage, it._mk(rt, acc))
-            it.locals["b"] = (storage, it._mk(rt, x))
-            res = it.to_storage(it.eval(expr, one), storage, one)
-            acc = res.v[0]
-    value = complex(acc) if rt == CFLOAT else float(acc) if rt in FLOAT_TYPES else int(acc)
-    return ReduceResult(value, op, rt, n, 0.0, 0.0, unsure, rt not in FLOAT_TYPES and rt != CFLOAT)
+        vals.append(val.v)
+        errs.append(val.e)
+    m = np.concatenate(vals) if vals else np.zeros(0, neutral_val.v.dtype)
+    e = np.concatenate(errs) if errs else np.zeros(0)
+    if rt not in FLOAT_TYPES and rt != CFLOAT:
+        acc = generic_prefix(sig.result, rt, combine, neutral_val.v[0], m)[-1]
+        return ReduceResult(int(acc), op, rt, n, 0.0, 0.0, unsure, True)
+    prefix = generic_prefix(sig.result, rt, combine, neutral_val.v[0], m)
+    rounds, slack = generic_float_model(sig.result, rt, combine, prefix, m)
+    acc = prefix[-1]
+    value = complex(acc) if rt == CFLOAT else float(acc)
+    abs_sum = float(np.sum(np.abs(m))) * (1 + 1e-12)
+    err_sum = float(np.sum(e)) * (1 + 1e-12)
+    exact = rounds == 0.0 and err_sum == 0.0 and slack == 0.0
+    return ReduceResult(value, op, rt, n, abs_sum, err_sum, unsure, exact, rounds, slack)
+
+
+def _combine_eval(storage, rt, expr, a, b, ea=0.0, eb=0.0):
+    """The reduce expression at every pair (a[k], b[k]) at once, the
+    operands carrying error bounds ea, eb; returns the interpreter's value
+    converted to the result type."""
+    L = len(a)
+    it = Interp({}, {}, np.zeros(L, np.int64), 1)
+    one = np.ones(L, bool)
+    it.locals["a"] = (storage, it._mk(rt, a, e=ea))
+    it.locals["b"] = (storage, it._mk(rt, b, e=eb))
+    return it.to_storage(it.eval(expr, one), storage, one)
+
+
+def generic_prefix(storage, rt, combine, neutral, m):
+    """Left-to-right fold neutral (+) m[0] (+) m[1] ...: every partial value
+    (entry k holds k map terms), each step evaluated with C semantics on the
+    result type (integers exact, floating values ideal in float64)."""
+    expr = parse_expression(combine)
+    acc = neutral
+    pref = [acc]
+    for x in m.tolist():
+        acc = _combine_eval(storage, rt, expr, np.asarray([acc]), np.asarray([x])).v[0]
+        pref.append(acc)
+    dt = np.complex128 if rt == CFLOAT else np.float64 if rt in FLOAT_TYPES else object
+    return np.array(pref, dtype=dt)
+
+
+TINY_OPERANDS = 2.0 ** -80
+
+
+def generic_float_model(storage, rt, combine, prefix, m):
+    """(rounds, slack) of the error model above for the steps
+    prefix[k] (+) m[k] of a floating fold; raises OracleError where a step
+    leaves the model (expansive, growing faster than a sum, or a neutral
+    element that is not an identity)."""
+    if m.size == 0:
+        return 0.0, 0.0
+    expr = parse_expression(combine)
+    # steps with an infinite or NaN operand (an infinite neutral element, say)
+    # have no rounding to bound: they are left out
+    fin = np.isfinite(prefix[:-1]) & np.isfinite(m)
+    if not np.any(fin):
+        return 0.0, 0.0
+    a, b = prefix[:-1][fin], m[fin]
+    u = UNIT[rt]
+    exact = _combine_eval(storage, rt, expr, a, b)
+    r = exact.e
+    mag = np.abs(a) + np.abs(b)
+    for which in ("a", "b"):
+        delta = np.maximum(mag, 1.0) * 2.0 ** -30
+        pert = _combine_eval(storage, rt, expr, a, b, *((delta, 0.0) if which == "a" else (0.0, delta)))
+        with np.errstate(invalid="ignore"):
+            sens = (pert.e - r) / delta
+        if np.any(~(sens <= (1 + u) * (1 + 2.0 ** -20))):
+            k = int(np.argmax(~(sens <= (1 + u) * (1 + 2.0 ** -20))))
+            raise OracleError(f"the reduce expression amplifies an error in '{which}' at step {k} "
+                              f"(sensitivity {sens[k]:.6g} > 1): no order-free bound")
+    with np.errstate(invalid="ignore"):
+        grows = ~(np.abs(exact.v) <= mag * (1 + 2.0 ** -40) + r)
+    if np.any(grows):
+        k = int(np.argmax(grows))
+        raise OracleError(f"|f(a, b)| exceeds |a| + |b| at step {k}: no order-free bound")
+    ident = _combine_eval(storage, rt, expr, np.full(b.size, prefix[0]), b)
+    with np.errstate(invalid="ignore"):
+        off = ~(np.abs(ident.v - b) <= ident.e)
+    if np.any(off):
+        k = int(np.argmax(off))
+        raise OracleError(f"the neutral element is not an identity of the reduce expression "
+                          f"(f(neutral, {b[k]!r}) = {ident.v[k]!r})")
+    big = mag >= TINY_OPERANDS
+    rounds = float(np.max(r[big] / (u * mag[big]))) if np.any(big) else 0.0
+    slack = float(np.max(r[~big])) * (b.size + 2 ** 14) if np.any(~big) else 0.0
+    return rounds, slack
 
 
 def exact_sum(values) -> float:
@@ -189,4 +305,4 @@ def norm2(values) -> float:
 
 
 __all__ = ["reduce", "canonical_op", "ReduceResult", "exact_sum", "norm2",
-           "eval_neutral", "LONG", "INT"]
+           "eval_neutral", "generic_prefix", "generic_float_model", "LONG", "INT"]

@@ -26,7 +26,10 @@ computes the order-free value of every prefix:
   every prefix (a NaN propagates to every later prefix; -0 orders below
   +0); of integers: exact;
 * any other combine: a left-to-right fold with C semantics on the result
-  type (pure Python; small n only).
+  type (pure Python; small n only); for floating results every prefix
+  carries the reductions' order-free error model (``reduce``): the device's
+  prefix i is within rounds * u * D * sum_{j<=i} |m_j| + sum_{j<=i} e_j +
+  slack of the oracle's, D being the depth of its combination tree.
 """
 
 from __future__ import annotations
@@ -39,7 +42,8 @@ from .api import map_chunks
 from .ctype import CFLOAT, FLOAT_TYPES, INT_RANGE, STORAGE_VT, UINT, parse_signature
 from .interp import Interp, OracleError
 from .parser import parse_expression
-from .reduce import GENERIC_FOLD_LIMIT, canonical_op, eval_neutral
+from .reduce import (GENERIC_FOLD_LIMIT, canonical_op, eval_neutral, generic_float_model,
+                     generic_prefix)
 
 
 @dataclass
@@ -52,6 +56,8 @@ class ScanResult:
     err_prefix: np.ndarray   # sum over the prefix of the map values' error bounds
     unsure: int              # lanes whose map value may legitimately differ on the GPU
     exact: bool              # whether the GPU result must match bit for bit
+    rounds: float = 1.0      # roundings per combination and unit operand magnitude
+    abs_slack: float = 0.0   # absolute allowance for steps with operands below 2**-80
 
 
 def _exact_float_prefix(neutral: float, values: np.ndarray) -> np.ndarray:
@@ -143,19 +149,19 @@ def scan(dtypes, map_expr, combine, neutral, n, args, exclusive=False) -> ScanRe
     else:
         if n > GENERIC_FOLD_LIMIT:
             raise OracleError("generic scans are evaluated for small n only")
-        expr = parse_expression(combine)
-        storage = sig.result
-        acc = neutral_val.v[0]
-        pref = [acc]
-        one = np.ones(1, bool)
-        for x in m.tolist():
-            it = Interp({}, {}, np.zeros(1, np.int64), 1)
-            it.locals["a"] = (storage, it._mk(rt, acc))
-            it.locals["b"] = (storage, it._mk(rt, x))
-            acc = it.to_storage(it.eval(expr, one), storage, one).v[0]
-            pref.append(acc)
-        prefix = np.array(pref, dtype=np.float64 if rt in FLOAT_TYPES else np.int64)
-        exact = rt not in FLOAT_TYPES
+        prefix = generic_prefix(sig.result, rt, combine, neutral_val.v[0], m)
+        exact = rt not in FLOAT_TYPES and rt != CFLOAT
+        if exact:
+            prefix = prefix.astype(np.int64)
+        else:
+            rounds, slack = generic_float_model(sig.result, rt, combine, prefix, m)
+            pad = 1.0 + (n + 1) * 2.0 ** -52
+            abs_p[1:] = np.cumsum(np.abs(m)) * pad
+            err_p[1:] = np.cumsum(e) * pad
+            exact = rounds == 0.0 and not np.any(e > 0) and slack == 0.0
+            sl = slice(0, n) if exclusive else slice(1, n + 1)
+            return ScanResult(prefix[sl], op, rt, n, abs_p[sl], err_p[sl], unsure, exact,
+                              rounds, slack)
 
     sl = slice(0, n) if exclusive else slice(1, n + 1)
     return ScanResult(prefix[sl], op, rt, n, abs_p[sl], err_p[sl], unsure, exact)

@@ -8,7 +8,7 @@ hash.  This package is its thin Python binding; PyTorch provides device
 memory and streams only.
 """
 
-from .hipmr import (JOB_NAMES, CFG_FORCE_SCALAR, Graph, Server, autotune_reduce, autotune_segmented,
+from .hipmr import (JOB_NAMES, CFG_FORCE_SCALAR, CFG_SEG_GLOBAL, CFG_TUNED, Graph, Server, autotune_reduce, autotune_segmented,
                     reduce_segmented, segmented_workspace_bytes, scan, scan_workspace_bytes, CFG_NONTEMPORAL, CFG_TEMPORAL, BudgetError, CompileError,
                     ElementwiseKernel, HipError, HipmrError, InvalidError, Kernel, LaunchConfig,
                     MismatchError, ParseError, ReductionKernel, UnsupportedError, WorkspaceError,
@@ -22,6 +22,7 @@ __all__ = ["ElementwiseKernel", "ReductionKernel", "Kernel", "compile", "element
            "autotune_segmented", "autotune_reduce", "Graph", "Server", "JOB_NAMES",
            "prepare_reduce", "reduce_workspace_bytes", "cache_stats", "cache_drop_memory",
            "sha256_hex", "selftest_compile", "lib", "torch_dtype", "LaunchConfig",
-           "CFG_NONTEMPORAL", "CFG_TEMPORAL", "CFG_FORCE_SCALAR", "HipmrError", "InvalidError",
+           "CFG_NONTEMPORAL", "CFG_TEMPORAL", "CFG_FORCE_SCALAR", "CFG_SEG_GLOBAL", "CFG_TUNED",
+           "HipmrError", "InvalidError",
            "ParseError", "CompileError", "HipError", "MismatchError", "UnsupportedError",
            "BudgetError", "WorkspaceError"]

@@ -7,6 +7,8 @@
 #include <cctype>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <unordered_map>
 
 #include "internal.h"
 
@@ -85,6 +87,9 @@ hipmr_status get_variant(hipmr_kernel* h, const KernelSpec& spec, std::shared_pt
             return HIPMR_OK;
         }
     }
+    if (no_alloc_now())
+        return fail(HIPMR_E_INVALID, "this kernel variant has not been built for the handle: run the "
+                                     "allocating entry point once with the same arguments first");
     std::string symbol;
     std::string src = render(h->prog, spec, &symbol);
     hipmr_status st;
@@ -153,15 +158,87 @@ int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap)
     return (int)std::max<long long>(g, 1);
 }
 
+// Handles are cached by (name, dtypes, expr) as given: compiling the same
+// text again returns the same handle with one more reference, which costs a
+// hash lookup (section "Core Method": kernels already built are reused
+// instead of being generated again).  The last hipmr_release removes the
+// handle from the cache and frees it.  All reference counting happens under
+// g_handles_mu, so a lookup never revives a handle that is being freed.
+std::mutex g_handles_mu;
+std::unordered_map<std::string, hipmr_kernel*> g_handles;
+
+std::string handle_key(const char* expr, const char* dtypes, const std::string& name) {
+    std::string k;
+    k.reserve(name.size() + std::strlen(dtypes) + std::strlen(expr) + 2);
+    k += name;
+    k += '\x1f';
+    k += dtypes;
+    k += '\x1f';
+    k += expr;
+    return k;
+}
+
+hipmr_status build_handle(const char* expr, const char* dtypes, const std::string& nm,
+                          std::unique_ptr<hipmr_kernel>* out);
+
 hipmr_status make_handle(const char* expr, const char* dtypes, const char* name,
                          hipmr_handle* out) {
     if (!expr || !dtypes || !out) return fail(HIPMR_E_INVALID, "NULL argument to hipmr_compile");
     *out = nullptr;
     std::string nm = name && *name ? name : "hipmr";
+    std::string key = handle_key(expr, dtypes, nm);
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        auto it = g_handles.find(key);
+        if (it != g_handles.end()) {
+            ++it->second->refs;
+            *out = it->second;
+            return HIPMR_OK;
+        }
+    }
+    std::unique_ptr<hipmr_kernel> h;
+    hipmr_status st = build_handle(expr, dtypes, nm, &h);      // front end, codegen, compile
+    if (st != HIPMR_OK) return st;
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    auto ins = g_handles.emplace(key, h.get());
+    if (!ins.second) {                 // another thread built the same handle meanwhile
+        ++ins.first->second->refs;
+        *out = ins.first->second;
+        return HIPMR_OK;
+    }
+    h->cache_key = key;
+    h->cached = true;
+    *out = h.release();
+    return HIPMR_OK;
+}
+
+void release_handle(hipmr_kernel* h) {
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        if (--h->refs > 0) return;
+        if (h->cached) {
+            auto it = g_handles.find(h->cache_key);
+            if (it != g_handles.end() && it->second == h) g_handles.erase(it);
+        }
+    }
+    delete h;
+}
+
+// Forgets the cached handles (they stay valid for their holders, who free
+// them with their last release); compile() then builds new ones.
+void drop_handle_cache() {
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    for (auto& kv : g_handles) kv.second->cached = false;
+    g_handles.clear();
+}
+
+hipmr_status build_handle(const char* expr, const char* dtypes, const std::string& nm,
+                          std::unique_ptr<hipmr_kernel>* out) {
     for (char c : nm)
         if (!(std::isalnum((unsigned char)c) || c == '_'))
             return fail(HIPMR_E_INVALID, "kernel name must be a C identifier");
     auto h = std::make_unique<hipmr_kernel>();
+    h->refs = 1;
     h->prog.name = nm;
     h->prog.expr = expr;
     hipmr_status st = parse_signature(dtypes, &h->prog.sig);
@@ -189,7 +266,7 @@ hipmr_status make_handle(const char* expr, const char* dtypes, const char* name,
         st = get_variant(h.get(), spec, &co);
         if (st != HIPMR_OK) return st;
     }
-    *out = h.release();
+    *out = std::move(h);
     return HIPMR_OK;
 }
 
@@ -482,7 +559,7 @@ hipmr_status hipmr_reduce_ex(hipmr_handle h, const char* map_expr, const char* c
     if (!workspace || workspace_bytes < hipmr_reduce_workspace_bytes(h, n))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_reduce_workspace_bytes()");
     hipmr_launch_config tuned{};
-    if (!cfgp && tuned_config(h, "reduce", combine, neutral, n, &tuned)) cfgp = &tuned;
+    cfgp = apply_tuned(h, "reduce", combine, neutral, n, cfgp, &tuned);
     LaunchCfg cfg;
     st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
     if (st != HIPMR_OK) return st;
@@ -529,7 +606,7 @@ hipmr_status hipmr_reduce(hipmr_handle h, const char* map_expr, const char* comb
 const char* hipmr_last_error(void) { return last_error(); }
 
 void hipmr_release(hipmr_handle h) {
-    if (h && h->refs.fetch_sub(1) == 1) delete h;
+    if (h) release_handle(h);
 }
 
 hipmr_status hipmr_get_handle_info(hipmr_handle h, hipmr_handle_info* info) {
@@ -628,7 +705,10 @@ hipmr_status hipmr_get_cache_stats(hipmr_cache_stats* out) {
     return HIPMR_OK;
 }
 
-void hipmr_cache_drop_memory(void) { cache_drop_memory(); }
+void hipmr_cache_drop_memory(void) {
+    drop_handle_cache();
+    cache_drop_memory();
+}
 
 hipmr_status hipmr_sha256_hex(const void* data, size_t len, char* out) {
     clear_error();

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -129,9 +130,11 @@ hipmr_status seg_launch(hipmr_kernel* h, const SegLaunch& L, int32_t nseg, const
     void* tile_start = workspace;
     void* tpart = (char*)workspace + align256((size_t)(nseg + 1) * 4);
     long long total = total_n, head = L.head;
+    // tile partials the workspace holds: the planner and both stages stop there
+    long long cap = max_tiles(nseg, total_n, L.cfg.vec);
     const void* off = d_offsets;
     int ns = nseg;
-    void* p_plan[5] = {&off, &ns, &total, &head, &tile_start};
+    void* p_plan[6] = {&off, &ns, &total, &head, &tile_start, &cap};
     hipmr_status st = launch(L.plan, 1, kPlanBlock, p_plan, stream);
     if (st != HIPMR_OK) return st;
     std::vector<void*> p1;
@@ -143,9 +146,10 @@ hipmr_status seg_launch(hipmr_kernel* h, const SegLaunch& L, int32_t nseg, const
     p1.push_back(&ns);
     p1.push_back(&tile_start);
     p1.push_back(&tpart);
+    p1.push_back(&cap);
     st = launch(L.s1, (unsigned)L.grid1, (unsigned)L.cfg.block, p1.data(), stream);
     if (st != HIPMR_OK) return st;
-    void* p2[4] = {&tile_start, &ns, &tpart, &d_out};
+    void* p2[5] = {&tile_start, &ns, &tpart, &d_out, &cap};
     unsigned grid2 = (unsigned)((nseg + kSegBlock / 64 - 1) / (kSegBlock / 64));
     return launch(L.s2, grid2, kSegBlock, p2, stream);
 }
@@ -159,6 +163,8 @@ hipmr_status seg_checks(hipmr_kernel* h, const char* combine, const char* neutra
     if (!combine || !neutral) return fail(HIPMR_E_INVALID, "combine_op and neutral are required");
     if (nseg < 0) return fail(HIPMR_E_INVALID, "nseg must be >= 0");
     if (nseg > 0 && (!d_offsets || !d_out)) return fail(HIPMR_E_INVALID, "offsets or out is NULL");
+    if (max_tiles(nseg, total_n, h->default_vec) > INT32_MAX)
+        return fail(HIPMR_E_UNSUPPORTED, "segmented reduce: more than 2^31 - 1 tiles (total_n too large)");
     if (nseg > 0 && (!workspace || ws_bytes < seg_workspace(nseg, total_n, h->default_vec)))
         return fail(HIPMR_E_WORKSPACE, "workspace smaller than hipmr_segmented_workspace_bytes()");
     return HIPMR_OK;
@@ -287,14 +293,62 @@ hipmr_status time_config(Run run, int reps, void* stream, float* ms) {
 }
 
 thread_local bool g_capturing = false;
+thread_local bool g_no_alloc = false;
 
 }  // namespace
 
 bool capturing_now() { return g_capturing; }
+bool no_alloc_now() { return g_no_alloc; }
+void set_no_alloc(bool on) { g_no_alloc = on; }
+
+size_t segmented_workspace(const hipmr_kernel* h, int32_t nseg, int64_t total_n) {
+    return seg_workspace(nseg, total_n, h->default_vec);
+}
+
+hipmr_status reduce_segmented_on(hipmr_kernel* h, const char* combine, const char* neutral,
+                                 int32_t nseg, const int64_t* d_offsets, int64_t total_n,
+                                 void* const* args, void* d_out, void* workspace,
+                                 size_t workspace_bytes, const hipmr_launch_config* cfgp,
+                                 void* stream) {
+    hipmr_status st = seg_checks(h, combine, neutral, nseg, d_offsets, total_n, args, d_out, workspace,
+                                 workspace_bytes);
+    if (st != HIPMR_OK) return st;
+    if (nseg == 0) return HIPMR_OK;
+    hipmr_launch_config tuned{};
+    cfgp = apply_tuned(h, "seg", combine, neutral, total_n, cfgp, &tuned);
+    LaunchCfg cfg;
+    st = resolve_cfg(cfgp, kSegBlock, kSegIpt, h->default_vec, kSegBlocksPerCu, &cfg);
+    if (st != HIPMR_OK) return st;
+    std::string syms;
+    SegLaunch L;
+    st = seg_prepare(h, combine, neutral, nseg, total_n, args, cfg, &syms, &L);
+    if (st != HIPMR_OK) return st;
+    set_last_symbols(h, syms);
+    return seg_launch(h, L, nseg, d_offsets, total_n, args, d_out, workspace, stream);
+}
 
 bool tuned_config(hipmr_kernel* h, const char* op, const char* combine, const char* neutral,
                   long long n, hipmr_launch_config* out) {
     return load_tuned(h, tune_key(op, combine, neutral), bucket_of(n), out);
+}
+
+const hipmr_launch_config* apply_tuned(hipmr_kernel* h, const char* op, const char* combine,
+                                       const char* neutral, long long n,
+                                       const hipmr_launch_config* cfgp, hipmr_launch_config* buf) {
+    if (!cfgp || !(cfgp->flags & HIPMR_CFG_TUNED)) return cfgp;
+    *buf = *cfgp;
+    buf->flags &= ~HIPMR_CFG_TUNED;
+    hipmr_launch_config t{};
+    LaunchCfg probe;
+    // a stored geometry that no longer resolves (an edited or stale file) is
+    // ignored: the caller's geometry applies
+    if (tuned_config(h, op, combine, neutral, n, &t) &&
+        resolve_cfg(&t, 256, 1, 1, 1, &probe) == HIPMR_OK) {
+        t.flags &= ~HIPMR_CFG_TUNED;
+        *buf = t;
+    }
+    clear_error();
+    return buf;
 }
 
 }  // namespace hipmr
@@ -312,21 +366,8 @@ hipmr_status hipmr_reduce_segmented(hipmr_handle h, const char* combine, const c
                                     size_t workspace_bytes, const hipmr_launch_config* cfgp,
                                     void* stream) {
     clear_error();
-    hipmr_status st = seg_checks(h, combine, neutral, nseg, d_offsets, total_n, args, d_out, workspace,
-                                 workspace_bytes);
-    if (st != HIPMR_OK) return st;
-    if (nseg == 0) return HIPMR_OK;
-    hipmr_launch_config tuned{};
-    if (!cfgp && load_tuned(h, tune_key("seg", combine, neutral), bucket_of(total_n), &tuned)) cfgp = &tuned;
-    LaunchCfg cfg;
-    st = resolve_cfg(cfgp, kSegBlock, kSegIpt, h->default_vec, kSegBlocksPerCu, &cfg);
-    if (st != HIPMR_OK) return st;
-    std::string syms;
-    SegLaunch L;
-    st = seg_prepare(h, combine, neutral, nseg, total_n, args, cfg, &syms, &L);
-    if (st != HIPMR_OK) return st;
-    set_last_symbols(h, syms);
-    return seg_launch(h, L, nseg, d_offsets, total_n, args, d_out, workspace, stream);
+    return reduce_segmented_on(h, combine, neutral, nseg, d_offsets, total_n, args, d_out, workspace,
+                               workspace_bytes, cfgp, stream);
 }
 
 hipmr_status hipmr_autotune_segmented(hipmr_handle h, const char* combine, const char* neutral,

@@ -937,16 +937,19 @@ __device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long lo
 
 // Planner: tiles per segment and their exclusive prefix, one block.  Each
 // thread takes 4 consecutive segments per round of 4096 (all offset loads
-// issued before any is used).
+// issued before any is used).  Counts are summed in 64 bits and every
+// written prefix is capped at the tile capacity of the workspace, so offsets
+// that describe more tiles than it holds (overlapping segments) can never
+// send a later kernel past it.
 const char* kSegPlan = R"HIP(
 extern "C" __global__ void __launch_bounds__(1024)
 @@KNAME@@(const long long* __restrict__ hipmr_off, int hipmr_nseg, long long hipmr_total,
-          long long hipmr_head, int* __restrict__ hipmr_tile_start)
+          long long hipmr_head, int* __restrict__ hipmr_tile_start, long long hipmr_cap)
 {
   constexpr int B = 1024, R = 4, V = @@VEC@@;
   constexpr long long T = 64LL * @@VEC@@ * @@IPT@@;
-  __shared__ int hipmr_wsum[B / 64];
-  __shared__ int hipmr_carry;
+  __shared__ long long hipmr_wsum[B / 64];
+  __shared__ long long hipmr_carry;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (threadIdx.x == 0) hipmr_carry = 0;
   __syncthreads();
@@ -955,7 +958,7 @@ extern "C" __global__ void __launch_bounds__(1024)
     long long o[R + 1];
 #pragma unroll
     for (int j = 0; j <= R; ++j) o[j] = s0 + j <= hipmr_nseg ? hipmr_off[s0 + j] : 0;
-    int t[R], tsum = 0;
+    long long t[R], tsum = 0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       t[j] = 0;
@@ -966,36 +969,36 @@ extern "C" __global__ void __launch_bounds__(1024)
       }
       tsum += t[j];
     }
-    int x = tsum;                                // inclusive scan in the wave
+    long long x = tsum;                          // inclusive scan in the wave
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-      const int y = __shfl_up(x, d, 64);
+      const long long y = __shfl_up(x, d, 64);
       if (l >= d) x += y;
     }
     if (l == 63) hipmr_wsum[w] = x;
     __syncthreads();
     if (w == 0) {                                // scan of the wave totals
-      int v = l < B / 64 ? hipmr_wsum[l] : 0;
+      long long v = l < B / 64 ? hipmr_wsum[l] : 0;
 #pragma unroll
       for (int d = 1; d < B / 64; d <<= 1) {
-        const int y = __shfl_up(v, d, 64);
+        const long long y = __shfl_up(v, d, 64);
         if (l >= d) v += y;
       }
       if (l < B / 64) hipmr_wsum[l] = v;
     }
     __syncthreads();
-    const int excl = hipmr_carry + (w > 0 ? hipmr_wsum[w - 1] : 0) + x - tsum;
-    int run = excl;
+    const long long excl = hipmr_carry + (w > 0 ? hipmr_wsum[w - 1] : 0) + x - tsum;
+    long long run = excl;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      if (s0 + j < hipmr_nseg) hipmr_tile_start[s0 + j] = run;
+      if (s0 + j < hipmr_nseg) hipmr_tile_start[s0 + j] = (int)(run < hipmr_cap ? run : hipmr_cap);
       run += t[j];
     }
     __syncthreads();
-    if (threadIdx.x == B - 1) hipmr_carry = excl + tsum;
+    if (threadIdx.x == B - 1) hipmr_carry = excl + tsum < hipmr_cap ? excl + tsum : hipmr_cap;
     __syncthreads();
   }
-  if (threadIdx.x == 0) hipmr_tile_start[hipmr_nseg] = hipmr_carry;
+  if (threadIdx.x == 0) hipmr_tile_start[hipmr_nseg] = (int)hipmr_carry;
 }
 )HIP";
 
@@ -1004,7 +1007,8 @@ const char* kSegS1 = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_total, long long hipmr_head,
           const long long* __restrict__ hipmr_offsets, int hipmr_nseg,
-          const int* __restrict__ hipmr_tile_start, hipmr_acc* __restrict__ hipmr_tpart)
+          const int* __restrict__ hipmr_tile_start, hipmr_acc* __restrict__ hipmr_tpart,
+          long long hipmr_cap)
 {
   typedef @@IDX@@ hipmr_idx;
   constexpr int HIPMR_B = @@BLOCK@@, HIPMR_U = @@IPT@@, HIPMR_V = @@VEC@@, HIPMR_LDS_SEGS = @@LDS_SEGS@@;
@@ -1025,7 +1029,9 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   auto hipmr_ts = [&](int hipmr_k) -> int {
     return hipmr_in_lds ? hipmr_ts_lds[hipmr_k] : hipmr_tile_start[hipmr_k];
   };
-  const int hipmr_total_tiles = hipmr_ts(hipmr_nseg);
+  // the planner caps the table at the workspace's tile capacity; the cap is
+  // applied here again so that no tile partial is written past it
+  const int hipmr_total_tiles = hipmr_ts(hipmr_nseg) < hipmr_cap ? hipmr_ts(hipmr_nseg) : (int)hipmr_cap;
   const int hipmr_nwaves = gridDim.x * (HIPMR_B / 64);
   // segment of a tile: the last s with tile_start[s] <= tile (64-way ballot search)
   auto hipmr_find = [&](int hipmr_tile) -> int {
@@ -1109,14 +1115,15 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 const char* kSegS2 = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(const int* __restrict__ hipmr_tile_start, int hipmr_nseg,
-          const hipmr_acc* __restrict__ hipmr_tpart, hipmr_acc* __restrict__ hipmr_out)
+          const hipmr_acc* __restrict__ hipmr_tpart, hipmr_acc* __restrict__ hipmr_out,
+          long long hipmr_cap)
 {
   const int s = blockIdx.x * (@@BLOCK@@ / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (s >= hipmr_nseg) return;                  // whole waves only
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   hipmr_acc r = hipmr_neutral;
-  const int t1 = hipmr_tile_start[s + 1];
+  const int t1 = hipmr_tile_start[s + 1] < hipmr_cap ? hipmr_tile_start[s + 1] : (int)hipmr_cap;
   // lane order t, t + 64, t + 128, ...; eight loads in flight per round
   for (int t = hipmr_tile_start[s] + lane; t < t1; t += 64 * 8) {
     hipmr_acc v[8];

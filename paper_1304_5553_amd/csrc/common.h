@@ -188,5 +188,9 @@ void cache_drop_memory();
 // True between hipmr_graph_begin_capture and hipmr_graph_end_capture on this
 // thread: code objects must already be loaded then.
 bool capturing_now();
+// true while a no-allocation entry point runs on this thread: variants are
+// neither built nor loaded then (only those already on the device are used)
+bool no_alloc_now();
+void set_no_alloc(bool on);
 
 }  // namespace hipmr

@@ -8,7 +8,9 @@
 #include "common.h"
 
 struct hipmr_kernel {
-    std::atomic<int> refs{1};
+    int refs = 1;                 // changed only under the handle cache's lock
+    bool cached = false;          // listed in the handle cache under cache_key
+    std::string cache_key;
     hipmr::Program prog;
     int default_vec = 4;
     std::mutex mu;
@@ -49,6 +51,20 @@ int grid_for(long long work_units, int per_block, const LaunchCfg& cfg, int cap)
 // geometry stored by the autotuner for (op, combine, neutral, size class of n)
 bool tuned_config(hipmr_kernel* h, const char* op, const char* combine, const char* neutral,
                   long long n, hipmr_launch_config* out);
+// cfgp with HIPMR_CFG_TUNED: the stored geometry when one exists and resolves,
+// else cfgp without the flag (copied into *buf); any other cfgp unchanged
+const hipmr_launch_config* apply_tuned(hipmr_kernel* h, const char* op, const char* combine,
+                                       const char* neutral, long long n,
+                                       const hipmr_launch_config* cfgp, hipmr_launch_config* buf);
+
+// the segmented map-reduce on a given workspace (hipmr_reduce_segmented's
+// body; the no-allocation entry point passes its static scratch array)
+size_t segmented_workspace(const hipmr_kernel* h, int32_t nseg, int64_t total_n);
+hipmr_status reduce_segmented_on(hipmr_kernel* h, const char* combine, const char* neutral,
+                                 int32_t nseg, const int64_t* d_offsets, int64_t total_n,
+                                 void* const* args, void* d_out, void* workspace,
+                                 size_t workspace_bytes, const hipmr_launch_config* cfgp,
+                                 void* stream);
 
 // device source of the serving loop's kernels
 std::string serve_source(const std::string& prefix);

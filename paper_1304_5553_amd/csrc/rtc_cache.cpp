@@ -207,6 +207,9 @@ hipmr_status get_function(CodeObject& co, void** fn) {
         if (capturing_now())
             return fail(HIPMR_E_INVALID, "kernel " + co.symbol + " is not loaded on this device yet: "
                                          "run the operation once before capturing it in a graph");
+        if (no_alloc_now())
+            return fail(HIPMR_E_INVALID, "kernel " + co.symbol + " is not loaded on this device yet: "
+                                         "run the allocating entry point once on this device first");
         hipModule_t m;
         e = hipModuleLoadData(&m, co.image.data());
         if (e != hipSuccess)

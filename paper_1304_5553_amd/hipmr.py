@@ -32,7 +32,7 @@ DTYPE_NAMES = {F32: "float", F64: "double", I8: "int8_t", U8: "uint8_t", I16: "i
                BF16: "bfloat16", F16: "half", FP8: "fp8_e4m3", C64: "complex64"}
 
 CFG_NONTEMPORAL, CFG_FORCE_SCALAR, CFG_TEMPORAL = 1, 2, 4
-CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES, CFG_SEG_GLOBAL = 8, 16, 32
+CFG_TEMPORAL_LOADS, CFG_TEMPORAL_STORES, CFG_SEG_GLOBAL, CFG_TUNED = 8, 16, 32, 64
 ACCESS_INDEX, ACCESS_SHIFTED, ACCESS_FIXED, ACCESS_OTHER = 1, 2, 4, 8
 
 
@@ -121,6 +121,9 @@ _SIGS = {
     "hipmr_segmented_workspace_bytes": (_SZ, [_VP, _I32, _I64]),
     "hipmr_reduce_segmented": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ,
                                       ctypes.POINTER(LaunchConfig), _VP]),
+    "hipmr_noalloc_scratch_bytes": (_SZ, []),
+    "hipmr_reduce_segmented_noalloc": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP,
+                                              ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_autotune_segmented": (_I32, [_VP, _CP, _CP, _I32, _VP, _I64, _VP, _VP, _VP, _SZ, _I32,
                                         ctypes.POINTER(LaunchConfig), _VP]),
     "hipmr_autotune_reduce": (_I32, [_VP, _CP, _CP, _I64, _VP, _VP, _VP, _SZ, _I32,
@@ -236,26 +239,47 @@ class Arg:
     __slots__ = ("name", "dtype", "pointer", "const", "read", "written", "access")
 
 
+_META = {}                # (expr, dtypes, name) -> the handle's metadata (a function of the text)
+_META_LOCK = threading.Lock()
+
+
 class Kernel:
-    """A compiled handle (the C ABI's hipmr_handle)."""
+    """A compiled handle (the C ABI's hipmr_handle).  compile() of text seen
+    before returns the library's cached handle with one more reference; its
+    metadata (argument types and access kinds) is a function of the text
+    and is kept here too, so a repeated compile costs one C call."""
 
     def __init__(self, expr, dtypes, name=None):
         self.expr = expr
         self.dtypes = dtypes
+        key = (expr, dtypes, name)
+        meta = _META.get(key)
         h = _VP()
-        if name is None:
-            _check(lib().hipmr_compile(expr.encode(), dtypes.encode(), ctypes.byref(h)))
+        if meta is not None:
+            fn, text = meta[-1]
+            st = fn(*text, ctypes.byref(h))
+            if st != OK:
+                _check(st)
         else:
-            _check(lib().hipmr_compile_named(expr.encode(), dtypes.encode(), name.encode(),
-                                             ctypes.byref(h)))
+            L = lib()
+            if name is None:
+                fn, text = L.hipmr_compile, (expr.encode(), dtypes.encode())
+            else:
+                fn, text = L.hipmr_compile_named, (expr.encode(), dtypes.encode(), name.encode())
+            _check(fn(*text, ctypes.byref(h)))
+            meta = self._metadata(h, dtypes) + ((fn, text),)
+            with _META_LOCK:
+                _META[key] = meta
         self._h = h
+        (self.is_reduce, self.result_dtype, self.vectorizable, self.vec, self.args,
+         self._sized, _) = meta
+        self._tls = threading.local()     # per-thread argument buffers (see marshal)
+
+    @staticmethod
+    def _metadata(h, dtypes):
         info = HandleInfo()
         _check(lib().hipmr_get_handle_info(h, ctypes.byref(info)))
-        self.is_reduce = bool(info.is_reduce)
-        self.result_dtype = info.result_dtype
-        self.vectorizable = bool(info.vectorizable)
-        self.vec = info.vec
-        self.args = []
+        args = []
         for k in range(info.nargs):
             vals = [_I32() for _ in range(5)]
             _check(lib().hipmr_get_arg_info(h, k, *[ctypes.byref(v) for v in vals]))
@@ -264,15 +288,16 @@ class Kernel:
             acc = _I32()
             _check(lib().hipmr_get_arg_access(h, k, ctypes.byref(acc)))
             a.access = acc.value
-            self.args.append(a)
+            args.append(a)
         names = [d.strip().replace("*", " ").split()[-1]
                  for d in dtypes.split(":", 1)[-1].split(",") if d.strip()]
-        for a, nm in zip(self.args, names):
+        for a, nm in zip(args, names):
             a.name = nm
         # arrays that must hold n elements (accessed at i or i +/- E)
-        self._sized = [k for k, a in enumerate(self.args)
-                       if a.pointer and a.access & (ACCESS_INDEX | ACCESS_SHIFTED)]
-        self._tls = threading.local()     # per-thread argument buffers (see marshal)
+        sized = [k for k, a in enumerate(args)
+                 if a.pointer and a.access & (ACCESS_INDEX | ACCESS_SHIFTED)]
+        return (bool(info.is_reduce), info.result_dtype, bool(info.vectorizable), info.vec,
+                tuple(args), sized)
 
     @property
     def handle(self):
@@ -345,6 +370,34 @@ def _enc(s):
     return None if s is None else s.encode()
 
 
+def _check_out(out, dtype_code, count, what):
+    """The output tensor the library will write `count` values of the
+    result type into: device memory of that dtype, contiguous, large
+    enough (the C ABI takes a bare pointer and cannot check any of it)."""
+    import torch
+    if not isinstance(out, torch.Tensor):
+        raise InvalidError(f"{what}: out must be a device tensor")
+    want = torch_dtype(dtype_code)
+    if out.dtype != want:
+        raise MismatchError(f"{what}: out has dtype {out.dtype}, the result type is {want}")
+    if not out.is_contiguous():
+        raise InvalidError(f"{what}: out must be contiguous")
+    if out.numel() < count:
+        raise InvalidError(f"{what}: out holds {out.numel()} elements, {count} are written")
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _check_offsets(offsets):
+    import torch
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64:
+        raise MismatchError("offsets must be a device tensor of int64")
+    if not offsets.is_contiguous() or offsets.dim() != 1 or offsets.numel() < 1:
+        raise InvalidError("offsets must be a contiguous 1-d tensor of nseg + 1 values")
+
+
 # --------------------------------------------------------------- C ABI names
 def compile(expr, dtypes, name=None) -> Kernel:   # noqa: A001 - the C ABI's name
     return Kernel(expr, dtypes, name)
@@ -380,6 +433,7 @@ def reduce_workspace_bytes(handle: Kernel, n):
 
 def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspace_buf=None,
            stream=None, config=None):   # noqa: A001 - the C ABI's name
+    _check_out(out, handle.result_dtype, 1, "reduce")
     s = _stream_ptr(stream)
     need = reduce_workspace_bytes(handle, n)
     if workspace_buf is None:
@@ -389,7 +443,7 @@ def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspac
     _check(lib().hipmr_reduce_ex(handle.handle, _enc(map_expr), _enc(combine_op), _enc(neutral),
                                  int(n), ptrs, ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(workspace_buf.data_ptr()),
-                                 workspace_buf.numel() * workspace_buf.element_size(),
+                                 _nbytes(workspace_buf),
                                  _config(config), s))
     return out
 
@@ -397,6 +451,7 @@ def reduce(handle: Kernel, map_expr, combine_op, neutral, n, args, out, workspac
 def _f64_out(out, args):
     import torch
     if out is not None:
+        _check_out(out, F64, 1, "compensated sum / norm")
         return out
     device = next((a.device for a in args if isinstance(a, torch.Tensor)), torch.device("cuda"))
     return torch.empty((), dtype=torch.float64, device=device)
@@ -414,7 +469,7 @@ def reduce_compensated(handle: Kernel, n, args, post_scale=1.0, out=None, worksp
     _check(lib().hipmr_reduce_compensated(handle.handle, int(n), ptrs, float(post_scale),
                                           ctypes.c_void_p(out.data_ptr()),
                                           ctypes.c_void_p(workspace_buf.data_ptr()),
-                                          workspace_buf.numel(), _config(config), s))
+                                          _nbytes(workspace_buf), _config(config), s))
     return out
 
 
@@ -429,7 +484,7 @@ def norm2(handle: Kernel, n, args, post_scale=1.0, passes=2, out=None, workspace
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_norm2(handle.handle, int(n), ptrs, float(post_scale), int(passes),
                              ctypes.c_void_p(out.data_ptr()),
-                             ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
+                             ctypes.c_void_p(workspace_buf.data_ptr()), _nbytes(workspace_buf),
                              _config(config), s))
     return out
 
@@ -442,6 +497,7 @@ def scan(handle: Kernel, combine_op, neutral, n, args, out, exclusive=False, wor
          stream=None, config=None):
     """out[i] = neutral (+) map(0) (+) ... (+) map(i) (inclusive) or up to
     map(i - 1) (exclusive); `out` is a device tensor of n result values."""
+    _check_out(out, handle.result_dtype, int(n), "scan")
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(scan_workspace_bytes(handle, n), out.device, s)
@@ -449,7 +505,7 @@ def scan(handle: Kernel, combine_op, neutral, n, args, out, exclusive=False, wor
     keep, ptrs = handle.marshal(args)
     _check(lib().hipmr_scan(handle.handle, combine_op.encode(), neutral.encode(), int(n), ptrs,
                             ctypes.c_void_p(out.data_ptr()), 1 if exclusive else 0,
-                            ctypes.c_void_p(workspace_buf.data_ptr()), workspace_buf.numel(),
+                            ctypes.c_void_p(workspace_buf.data_ptr()), _nbytes(workspace_buf),
                             _config(config), s))
     return out
 
@@ -462,7 +518,9 @@ def reduce_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, args
                      workspace_buf=None, stream=None, config=None):
     """out[s] = fold of map(i) over i in [offsets[s], offsets[s+1]) (device
     int64 offsets, nseg + 1 of them)."""
+    _check_offsets(offsets)
     nseg = offsets.numel() - 1
+    _check_out(out, handle.result_dtype, nseg, "reduce_segmented")
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
@@ -472,7 +530,29 @@ def reduce_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, args
                                         ctypes.c_void_p(offsets.data_ptr()), int(total_n), ptrs,
                                         ctypes.c_void_p(out.data_ptr()),
                                         ctypes.c_void_p(workspace_buf.data_ptr()),
-                                        workspace_buf.numel(), _config(config), s))
+                                        _nbytes(workspace_buf), _config(config), s))
+    return out
+
+
+def noalloc_scratch_bytes():
+    """Bytes of the library's static scratch array (per device)."""
+    return lib().hipmr_noalloc_scratch_bytes()
+
+
+def reduce_segmented_noalloc(handle: Kernel, combine_op, neutral, offsets, total_n, args, out,
+                             stream=None, config=None):
+    """reduce_segmented without a workspace and without any allocation: the
+    tile table and partials live in the library's static scratch array.  Run
+    reduce_segmented once on the device with the same arguments first."""
+    _check_offsets(offsets)
+    nseg = offsets.numel() - 1
+    _check_out(out, handle.result_dtype, nseg, "reduce_segmented_noalloc")
+    handle.check_lengths(int(total_n), args)
+    keep, ptrs = handle.marshal(args)
+    _check(lib().hipmr_reduce_segmented_noalloc(handle.handle, combine_op.encode(), neutral.encode(),
+                                                nseg, ctypes.c_void_p(offsets.data_ptr()),
+                                                int(total_n), ptrs, ctypes.c_void_p(out.data_ptr()),
+                                                _config(config), _stream_ptr(stream)))
     return out
 
 
@@ -480,7 +560,9 @@ def autotune_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, ar
                        reps=10, workspace_buf=None, stream=None):
     """Times the candidate geometries on this data and stores the fastest;
     returns it as a dict."""
+    _check_offsets(offsets)
     nseg = offsets.numel() - 1
+    _check_out(out, handle.result_dtype, nseg, "autotune_segmented")
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(segmented_workspace_bytes(handle, nseg, total_n), out.device, s)
@@ -491,12 +573,13 @@ def autotune_segmented(handle: Kernel, combine_op, neutral, offsets, total_n, ar
                                           ctypes.c_void_p(offsets.data_ptr()), int(total_n), ptrs,
                                           ctypes.c_void_p(out.data_ptr()),
                                           ctypes.c_void_p(workspace_buf.data_ptr()),
-                                          workspace_buf.numel(), int(reps), ctypes.byref(best), s))
+                                          _nbytes(workspace_buf), int(reps), ctypes.byref(best), s))
     return {f: getattr(best, f) for f, _ in LaunchConfig._fields_}
 
 
 def autotune_reduce(handle: Kernel, combine_op, neutral, n, args, out, reps=10,
                     workspace_buf=None, stream=None):
+    _check_out(out, handle.result_dtype, 1, "autotune_reduce")
     s = _stream_ptr(stream)
     if workspace_buf is None:
         workspace_buf = workspace(reduce_workspace_bytes(handle, n), out.device, s)
@@ -506,7 +589,7 @@ def autotune_reduce(handle: Kernel, combine_op, neutral, n, args, out, reps=10,
     _check(lib().hipmr_autotune_reduce(handle.handle, combine_op.encode(), neutral.encode(), int(n),
                                        ptrs, ctypes.c_void_p(out.data_ptr()),
                                        ctypes.c_void_p(workspace_buf.data_ptr()),
-                                       workspace_buf.numel(), int(reps), ctypes.byref(best), s))
+                                       _nbytes(workspace_buf), int(reps), ctypes.byref(best), s))
     return {f: getattr(best, f) for f, _ in LaunchConfig._fields_}
 
 

@@ -234,6 +234,40 @@ def test_compile_cache_memory_and_disk(tmp_path, monkeypatch):
     assert s3["disk_hits"] == s2["disk_hits"] + 1 and s3["compiles"] == s2["compiles"]
 
 
+def test_compile_returns_the_cached_handle_and_release_balances():
+    """compile() of the same (name, dtypes, expression) while a reference is
+    held returns the same handle and touches neither the front end nor the
+    code-object cache; once every reference is released the next compile()
+    builds a new handle (its code object found in the memory cache)."""
+    import gc
+    tag = os.urandom(4).hex()
+    expr, sig = f"z[i] = x[i] + {int(tag, 16) % 9973}", "float *z, const float *x"
+    k1 = hm.compile(expr, sig, name="cached")
+    s0 = hm.cache_stats()
+    k2 = hm.compile(expr, sig, name="cached")
+    k3 = hm.compile(expr, sig, name="cached")
+    assert k1.handle.value == k2.handle.value == k3.handle.value
+    assert hm.cache_stats() == s0                          # a handle hit: no cache lookup at all
+    other = hm.compile(expr, sig, name="cached_other")     # another name is another handle
+    assert other.handle.value != k1.handle.value
+    del k2, k3
+    gc.collect()
+    k4 = hm.compile(expr, sig, name="cached")              # k1 still holds a reference
+    assert k4.handle.value == k1.handle.value and hm.cache_stats()["memory_hits"] == s0["memory_hits"]
+    del k1, k4
+    gc.collect()
+    s1 = hm.cache_stats()
+    k5 = hm.compile(expr, sig, name="cached")              # all released: built again
+    s2 = hm.cache_stats()
+    assert s2["memory_hits"] == s1["memory_hits"] + 1 and s2["compiles"] == s1["compiles"]
+    # after the memory caches are dropped, compile() builds a new handle (from disk)
+    hm.cache_drop_memory()
+    k6 = hm.compile(expr, sig, name="cached")
+    assert k6.handle.value != k5.handle.value
+    assert hm.cache_stats()["disk_hits"] == s2["disk_hits"] + 1
+    del k5, k6, other
+
+
 def test_corrupt_disk_entry_is_rebuilt():
     cache = os.environ.get("HIPMR_CACHE_DIR") or os.path.join(
         os.environ.get("XDG_CACHE_HOME") or os.path.expanduser("~/.cache"), "hipmr")

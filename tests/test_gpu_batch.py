@@ -197,16 +197,23 @@ def test_autotune_segmented_and_reduce(dev, seg_data, handles):
     best = hm.autotune_segmented(handles["sum"], "a+b", "0", od, x.size, [xd, yd],
                                  torch.empty(len(offsets) - 1, device=dev), reps=3)
     assert best["block"] in (256, 512) and best["items_per_thread"] in (1, 2, 4, 8)
-    got = run_seg(handles["sum"], "sum", od, x.size, [xd, yd])      # uses the tuned geometry
+    got = run_seg(handles["sum"], "sum", od, x.size, [xd, yd], config={"flags": hm.CFG_TUNED})
     check_segments("sum", got, offsets, x, y, "tuned sum", stride=7)
     k = hm.compile("x[i]*y[i]", "float: const float *x, const float *y", name="tuned_dot")
     out = torch.empty((), device=dev)
+    default = torch.empty((), device=dev)
+    hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], default)
     best = hm.autotune_reduce(k, "a+b", "0", x.size, [xd, yd], out, reps=3)
     assert best["block"] in (256, 512)
-    hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], out)
+    hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], out, config={"flags": hm.CFG_TUNED})
     r = oracle.reduce("float: const float *x, const float *y", "x[i]*y[i]", "a+b", "0", x.size,
                       [x, y])
     assert_reduce(out.item(), r, "tuned dot")
+    # without the flag a stored geometry is never applied: the default result is unchanged
+    again = torch.empty((), device=dev)
+    hm.reduce(k, None, "a+b", "0", x.size, [xd, yd], again)
+    torch.cuda.synchronize()
+    assert again.item() == default.item()
 
 
 def test_one_handle_across_tile_table_sizes(dev):
@@ -246,3 +253,37 @@ def test_segments_without_common_alignment(dev):
         r = oracle.reduce("double: const float *x, const float *y", "x[i]*y[i]", "a+b", "0",
                           b - a, [x[a:b], y[a:b]])
         assert_reduce(float(g[s]), r, f"unaligned segment {s}")
+
+
+def test_overlapping_offsets_stay_inside_the_workspace(dev):
+    """Offsets that are not non-decreasing ([0, N, 0, N, ...]: every other
+    segment covers the whole array) describe about nseg/2 * N / T tiles,
+    far more than the workspace's capacity nseg + N / 64 + 1.  The planner
+    caps the table there: nothing past the workspace is written (a canary
+    after it stays intact), and the segments whose tiles all lie below the
+    cap are still exact against the oracle."""
+    rng = np.random.default_rng(71)
+    N, nseg = 1 << 20, 64
+    x = rng.uniform(-1, 1, N).astype(np.float32)
+    offsets = np.array([0 if s % 2 == 0 else N for s in range(nseg + 1)], dtype=np.int64)
+    k = hm.compile("x[i]", "float: const float *x", name="overlap_sum")
+    need = hm.segmented_workspace_bytes(k, nseg, N)
+    ws = torch.full((need + 65536,), 0x5A, dtype=torch.uint8, device=dev)
+    out = torch.full((nseg,), float("nan"), device=dev)
+    hm.reduce_segmented(k, "max(a,b)", "-INFINITY", torch.from_numpy(offsets).to(dev), N,
+                        [dev_array(x)], out, workspace_buf=ws[:need])
+    torch.cuda.synchronize()
+    assert bool(torch.all(ws[need:] == 0x5A)), "written past the workspace"
+    g = host_bits(out)
+    tile = 64 * 4 * 4                      # default geometry: T = 64 lanes x 4 floats x 4 chunks
+    cap = nseg + (N + 63) // 64 + 1
+    full = cap // (N // tile)             # whole-array segments that fit below the cap
+    want = float(np.max(x))
+    checked = 0
+    for s in range(0, nseg, 2):
+        if s // 2 < full:
+            assert g[s] == want, s
+            checked += 1
+    assert checked >= 8
+    for s in range(1, nseg, 2):            # decreasing pairs are empty segments
+        assert g[s] == -np.inf or s // 2 >= full

@@ -130,3 +130,38 @@ def test_conj_that_does_not_conjugate(monkeypatch):
     monkeypatch.setattr(interp.Interp, "_complex_call", planted)
     assert caught(complex_pins.test_conjugated_dot_is_the_exact_sum)
     assert caught(complex_pins.test_gaussian_integer_products_are_exact)
+
+
+def test_generic_fold_bound_dropped(monkeypatch):
+    """The generic float fold's rounding allowance dropped (rounds = 0): the
+    fold would claim to be exact, and float32 folds along real trees leave it."""
+    import test_oracle_generic_fold as gf
+    monkeypatch.setattr(REDUCE_MOD, "generic_float_model", lambda *a, **k: (0.0, 0.0))
+    assert caught(gf.test_model_bounds_float32_folds_in_every_tree, "(a)+(b)", gf.PLUS, "uniform")
+    assert caught(gf.test_rounds_per_combination)
+
+
+def test_generic_fold_bound_too_small(monkeypatch):
+    """A bound four times too small (rounds / 4) is caught by the one-sided
+    rounding sequence that uses half of the true bound."""
+    import test_oracle_generic_fold as gf
+    real = REDUCE_MOD.generic_float_model
+
+    def planted(*a, **k):
+        rounds, slack = real(*a, **k)
+        return rounds / 4, slack
+    monkeypatch.setattr(REDUCE_MOD, "generic_float_model", planted)
+    assert caught(gf.test_model_bound_is_not_vacuous)
+
+
+def test_generic_fold_last_term_dropped(monkeypatch):
+    """A generic fold that skips its last map value is caught by the pin that
+    holds the fold to the correctly rounded sum."""
+    import test_oracle_generic_fold as gf
+    real = REDUCE_MOD.generic_prefix
+
+    def planted(storage, rt, combine, neutral, m):
+        p = real(storage, rt, combine, neutral, m[:-1])
+        return np.append(p, p[-1:]) if m.size else p
+    monkeypatch.setattr(REDUCE_MOD, "generic_prefix", planted)
+    assert caught(gf.test_sum_like_value_is_the_correctly_rounded_sum, "(a)+(b)")
