@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -47,10 +48,14 @@ def parse():
                         "(compile, dot, precision, batched, served, scan, shifted, cg, lazy, complex)")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
-    p.add_argument("--serving-duration", type=float, default=5.0,
+    p.add_argument("--serving-duration", type=float, default=4.0,
                    help="measured seconds of each serving rate (after 1 s of warm-up)")
-    p.add_argument("--cpu-sample", type=int, default=1 << 27,
-                   help="elements per op for the oracle timing")
+    p.add_argument("--cpu-sample", type=int, default=1 << 28,
+                   help="elements per op for the all-core oracle timing")
+    p.add_argument("--cpu-sample-one", type=int, default=1 << 25,
+                   help="elements per op for the one-core oracle timing")
+    p.add_argument("--no-accuracy", action="store_true",
+                   help="skip checking the timed results against the oracle")
     p.add_argument("--ops", default="E1,E2,R1,R2,R3",
                    help="comma list of E1,E2,R1,R2,R3 and COPY (z[i] = x[i], the plain copy "
                         "kernel used to calibrate the HBM byte counters)")
@@ -78,28 +83,328 @@ def counter_traffic(symbol):
     return None
 
 
-def cpu_baseline(x, y, k, sample):
-    """The oracle (test infrastructure) timed on the first `sample` elements
-    of every op; reported as algorithmic GB/s of that sample."""
+# ---------------------------------------------------------------- CPU leg
+# The oracle (test infrastructure) runs only in this leg: timed on this host's
+# cores as the CPU baseline, and as the checker of the results the timed GPU
+# runs produced.  The leg's worker processes are forked before the GPU is
+# touched, so they hold no device state; they share the plain workload's host
+# arrays (and two buffers for the GPU's elementwise outputs) copy-on-write and
+# regenerate the other workloads from the same seeds, i.e. the same bytes the
+# GPU read.
+
+_LEG = {}                   # set in the parent before the fork, read by the workers
+MAX_LEG_WORKERS = 16        # the CPU share of one GPU on the measurement hosts
+SERVE_MAPS = {0: "x[i]", 1: "x[i]*y[i]", 2: "x[i]*x[i]", 3: "x[i]", 4: "2.5f*x[i] - 0.5f*y[i]",
+              5: "x[i] > 0.0f", 6: "x[i]*x[i]", 7: "w[i]*x[i]"}
+SEG_OPS = {"sum": ("float: const float *x, const float *y", "x[i]", "a+b", "0"),
+           "max": ("float: const float *x, const float *y", "x[i]", "max(a,b)", "-INFINITY"),
+           "dot": ("float: const float *x, const float *y", "x[i]*y[i]", "a+b", "0")}
+GATE_REL = 2e-6             # float sums: |gpu - oracle| <= 2e-6 * sum |terms|
+PREC_UQ = {"bfloat16": 2.0 ** -8, "float16": 2.0 ** -11, "fp8_e4m3": 2.0 ** -4}
+PREC_MIN_SUB = {"bfloat16": 2.0 ** -133, "float16": 2.0 ** -24, "fp8_e4m3": 2.0 ** -9}
+PREC_MIN_NORMAL = {"bfloat16": 2.0 ** -126, "float16": 2.0 ** -14, "fp8_e4m3": 2.0 ** -6}
+
+
+def _leg_inputs(key):
+    """The seeded inputs of one workload, made once per worker."""
+    import workloads
+    cache = _LEG.setdefault("cache", {})
+    if key not in cache:
+        if key == "dot":
+            cache[key] = workloads.dot_1m()
+        elif key == "segments":
+            cache[key] = workloads.segments()
+        elif key == "pool":
+            cache[key] = workloads.serving_pool()
+        elif key[0] == "schedule":
+            cache[key] = workloads.serving_schedule(key[1], key[2])
+        elif key[0] == "precision":
+            for other in [c for c in cache if c[0] == "precision"]:
+                del cache[other]                       # one case (1 GiB) at a time
+            cache[key] = workloads.precision_values(workloads.N_PRECISION, key[1])
+    return cache[key]
+
+
+def _ratio(err, tol):
+    return 0.0 if err == 0 else (err / tol if tol > 0 else float("inf"))
+
+
+def leg_time_plain(a, b):
+    """Seconds the oracle takes for elements [a, b) of every plain op."""
     import oracle
     import workloads
-    m = min(sample, x.size)
-    xs, ys, ks = x[:m], y[:m], k[:m]
+    x, y, k = _LEG["x"][a:b], _LEG["y"][a:b], _LEG["k"][a:b]
+    m = b - a
     zero = np.zeros(1, np.float32)
-    c0 = time.process_time()
     t0 = time.perf_counter()
-    oracle.elementwise(workloads.E1[0], workloads.E1[1], m, [zero, xs, ys])
-    oracle.elementwise(workloads.E2[0], workloads.E2[1], m, [zero, xs, ys])
+    oracle.elementwise(workloads.E1[0], workloads.E1[1], m, [zero, x, y])
+    oracle.elementwise(workloads.E2[0], workloads.E2[1], m, [zero, x, y])
     for sig, mp, comb, neu in (workloads.R_COUNT, workloads.R_SUM):
-        oracle.reduce(sig, mp, comb, neu, m, [ks])
-    oracle.reduce(workloads.R_MAX[0], workloads.R_MAX[1], "max(a,b)", "-INFINITY", m, [xs])
-    dt = time.perf_counter() - t0
-    busy = (time.process_time() - c0) / dt     # CPU seconds per second: threads in use
-    nbytes = m * (12 + 12 + 4 + 4 + 4)
-    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": max(1, round(busy)),
-            "cpu_s_per_s": round(busy, 2), "kind": "oracle",
-            "sample": f"first {m} elements of each of E1, E2, R1, R2, R3 "
-                      f"({nbytes / 1e6:.0f} MB algorithmic) in {dt:.1f} s"}
+        oracle.reduce(sig, mp, comb, neu, m, [k])
+    oracle.reduce(workloads.R_MAX[0], workloads.R_MAX[1], "max(a,b)", "-INFINITY", m, [x])
+    return time.perf_counter() - t0
+
+
+def leg_check_elementwise(name, a, b):
+    """GPU output lanes [a, b) of E1 / E2 against the oracle: (lanes checked,
+    lanes outside twice the oracle's per-lane bound, largest |gpu - oracle| /
+    (2 bound))."""
+    import oracle
+    import workloads
+    sig, stmt = workloads.E1 if name == "E1" else workloads.E2
+    g = _LEG["z"][name][a:b].astype(np.float64)
+    ref = oracle.elementwise(sig, stmt, _LEG["n"], [np.zeros(1, np.float32), _LEG["x"], _LEG["y"]],
+                             lanes=np.arange(a, b))["z"]
+    ok = ~ref.u & ref.written
+    diff = np.abs(g - ref.v)
+    same = (g == ref.v) | (np.isnan(g) & np.isnan(ref.v))
+    bound = 2 * ref.e
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(same, 0.0, np.where(bound > 0, diff / bound, np.inf))
+    ratio = ratio[ok]
+    return int(ok.sum()), int(np.count_nonzero(ratio > 1)), float(ratio.max()) if ratio.size else 0.0
+
+
+def leg_plain_reduce(a, b):
+    """The oracle's count, sum and max over elements [a, b) (exact values)."""
+    import oracle
+    import workloads
+    x, k = _LEG["x"][a:b], _LEG["k"][a:b]
+    m = b - a
+    vals = [oracle.reduce(sig, mp, comb, neu, m, [k]).value
+            for sig, mp, comb, neu in (workloads.R_COUNT, workloads.R_SUM)]
+    vals.append(oracle.reduce(workloads.R_MAX[0], workloads.R_MAX[1], "max(a,b)", "-INFINITY",
+                              m, [x]).value)
+    return vals
+
+
+def leg_check_dot(g):
+    import oracle
+    import workloads
+    x, y = _leg_inputs("dot")
+    r = oracle.reduce(workloads.DOT[0], workloads.DOT[1], "a+b", "0", x.size, [x, y])
+    err = abs(g - r.value)
+    return {"n": int(x.size), "gpu": g, "oracle": r.value, "abs_err": err,
+            "sum_abs_terms": r.abs_sum, "err_over_sum_abs_terms": err / r.abs_sum,
+            "gate": GATE_REL, "ok": bool(err <= GATE_REL * r.abs_sum)}
+
+
+def leg_check_precision(fmt, case, g_sum, g_norm):
+    """The compensated sum and two-pass norm of one format and case against
+    the oracle: (i) the accumulation error against the exact sum / norm of
+    the stored (dequantised) values, relative to sum |q| / the norm, gate
+    1e-6; (ii) the total error against the float32 values before rounding to
+    the format, relative to sum |v| / |v|, gate u_q (plus the subnormal
+    allowance and gate (i))."""
+    import oracle
+    import workloads
+    v64 = _leg_inputs(("precision", case))
+    qz = workloads.quantize(fmt, v64)
+    decode = {"bfloat16": oracle.decode_bf16, "float16": oracle.decode_f16,
+              "fp8_e4m3": oracle.decode_e4m3fn}[fmt]
+    q = decode(qz.bits)
+    inv = 1.0 / qz.scale
+    o_sum, o_norm = oracle.exact_sum(q) * inv, oracle.norm2(q) * inv
+    abs_q = float(np.sum(np.abs(q))) * inv
+    v = qz.original.astype(np.float64) * inv
+    v_sum, v_norm = oracle.exact_sum(v), oracle.norm2(v)
+    abs_v = float(np.sum(np.abs(v)))
+    n_sub = int(np.count_nonzero(np.abs(q) < PREC_MIN_NORMAL[fmt]))
+    half_sub = PREC_MIN_SUB[fmt] / 2 * inv
+    gate_i_sum, gate_i_norm = 1e-6 * abs_q, 1e-6 * o_norm
+    gate_ii_sum = PREC_UQ[fmt] * abs_v + n_sub * half_sub + gate_i_sum
+    gate_ii_norm = PREC_UQ[fmt] * v_norm + math.sqrt(n_sub) * half_sub + gate_i_norm
+    e = {"sum_err_i": abs(g_sum - o_sum), "norm_err_i": abs(g_norm - o_norm),
+         "sum_err_ii": abs(g_sum - v_sum), "norm_err_ii": abs(g_norm - v_norm)}
+    return {"sum": g_sum, "norm2": g_norm, "oracle_sum": o_sum, "oracle_norm2": o_norm,
+            "sum_err_i_rel": e["sum_err_i"] / abs_q, "norm_err_i_rel": e["norm_err_i"] / o_norm,
+            "sum_err_ii_rel": e["sum_err_ii"] / abs_v, "norm_err_ii_rel": e["norm_err_ii"] / v_norm,
+            "gate_i_rel": 1e-6, "gate_ii_rel": PREC_UQ[fmt], "subnormal_or_zero": n_sub,
+            "ok": bool(e["sum_err_i"] <= gate_i_sum and e["norm_err_i"] <= gate_i_norm and
+                       e["sum_err_ii"] <= gate_ii_sum and e["norm_err_ii"] <= gate_ii_norm)}
+
+
+def leg_check_segments(op, s0, s1, g):
+    """Segments [s0, s1) of one segmented op against the oracle: (largest
+    |gpu - oracle| / (2e-6 sum |terms|), results outside the gate; max is
+    compared exactly)."""
+    import oracle
+    offsets, x, y = _leg_inputs("segments")
+    sig, mp, comb, neu = SEG_OPS[op]
+    worst, bad = 0.0, 0
+    for s in range(s0, s1):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        r = oracle.reduce(sig, mp, comb, neu, b - a, [x[a:b], y[a:b]])
+        gv = float(g[s - s0])
+        if r.exact or (r.op in ("max", "min") and r.err_sum == 0):
+            bad += int(not (gv == r.value or (math.isnan(gv) and math.isnan(r.value))))
+        else:
+            q = _ratio(abs(gv - r.value), GATE_REL * r.abs_sum)
+            worst = max(worst, q)
+            bad += int(q > 1)
+    return worst, bad
+
+
+def leg_check_served(rate, duration_s, idx, got):
+    """Served jobs idx (results got) of one rate against the oracle: (largest
+    error / gate, jobs outside the gate).  max and count are exact; sums use
+    |g - o| <= 2e-6 sum|t| + 2 sum(e), carried through the square root of the
+    norm and the ratio of the weighted mean."""
+    import oracle
+    f32, bf16 = _leg_inputs("pool")
+    sched = _leg_inputs(("schedule", rate, duration_s))
+    worst, bad = 0.0, 0
+    for k, g in zip(idx, got):
+        n, t, off = int(sched["n"][k]), int(sched["tmpl"][k]), int(sched["offset"][k])
+        fmt = "bfloat16" if sched["bf16"][k] else "float"
+        src = bf16 if sched["bf16"][k] else f32
+        arrs = [src[a][off:off + n] for a in ("x", "y", "w")]
+        sig = f"float: const {fmt} *x, const {fmt} *y, const {fmt} *w"
+        if t in (3, 5):
+            r = (oracle.reduce(sig, "x[i]", "max", "-INFINITY", n, arrs) if t == 3 else
+                 oracle.reduce(sig.replace("float:", "long:"), SERVE_MAPS[5], "a+b", "0", n, arrs))
+            bad += int(g != r.value)
+            continue
+        r = oracle.reduce(sig, SERVE_MAPS[t], "a+b", "0", n, arrs)
+        tol = GATE_REL * r.abs_sum + 2 * r.err_sum
+        if t == 2:
+            o = math.sqrt(r.value)
+            tol = tol / max(g + o, 1e-300) + 1e-300
+        elif t == 7:
+            den = oracle.reduce(sig, "w[i]", "a+b", "0", n, arrs)
+            o = r.value / den.value
+            tol = (tol + abs(o) * GATE_REL * den.abs_sum) / den.value
+        else:
+            o = r.value
+        q = _ratio(abs(g - o), tol)
+        worst = max(worst, q)
+        bad += int(q > 1)
+    return worst, bad
+
+
+def _chunks(n, parts):
+    step = -(-n // max(1, parts))
+    return [(a, min(a + step, n)) for a in range(0, n, step)]
+
+
+class CpuLeg:
+    """The oracle's worker processes (forked at construction, before the
+    GPU is touched), the baseline timing and the accuracy checks."""
+
+    def __init__(self, x, y, k, n):
+        import mmap
+        import multiprocessing
+        self.host_cpus = len(os.sched_getaffinity(0))
+        self.cores = max(1, min(MAX_LEG_WORKERS, self.host_cpus))
+        _LEG.update(x=x, y=y, k=k, n=n, z={})
+        self._maps = []
+        for name in ("E1", "E2"):
+            mm = mmap.mmap(-1, 4 * n)                # anonymous, shared with the workers
+            self._maps.append(mm)
+            _LEG["z"][name] = np.frombuffer(mm, dtype=np.float32, count=n)
+        self.pool = multiprocessing.get_context("fork").Pool(self.cores)
+
+    def close(self):
+        self.pool.terminate()
+        self.pool.join()
+
+    def baseline(self, sample_one, sample_all, reps=3):
+        """Median of `reps` runs of the oracle on one core (the first
+        sample_one elements of every plain op) and on all the leg's cores
+        (the first sample_all elements, one contiguous chunk per worker)."""
+        n = _LEG["n"]
+        m1, ma = min(sample_one, n), min(sample_all, n)
+        one = [self.pool.apply(leg_time_plain, (0, m1)) for _ in range(reps)]
+        chunks = _chunks(ma, self.cores)
+        allc = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            self.pool.starmap(leg_time_plain, chunks)
+            allc.append(time.perf_counter() - t0)
+        per = 12 + 12 + 4 + 4 + 4
+        t1, ta = float(np.median(one)), float(np.median(allc))
+        return {"value": round(ma * per / ta / 1e9, 3), "unit": "GB/s", "cores": self.cores,
+                "host_cpus": self.host_cpus, "kind": "oracle", "median_of": reps,
+                "sample": f"first {ma} elements of each of E1, E2, R1, R2, R3 "
+                          f"({ma * per / 1e6:.0f} MB algorithmic), one chunk per worker process, "
+                          f"{ta:.2f} s",
+                "single_core": {"value": round(m1 * per / t1 / 1e9, 3), "unit": "GB/s",
+                                "sample": f"first {m1} elements of each op, {t1:.2f} s"}}
+
+    def accuracy(self, checks):
+        """Every result the timed GPU runs left in `checks`, against the oracle."""
+        pool, jobs, out = self.pool, [], {}
+
+        def submit(key, fn, *args):
+            jobs.append((key, pool.apply_async(fn, args)))
+
+        for (fmt, case), (gs, gn) in checks.get("precision", {}).items():
+            submit(("precision", fmt, case), leg_check_precision, fmt, case, gs, gn)
+        for rate, row in checks.get("served", {}).items():
+            for part in np.array_split(np.arange(len(row["idx"])), 8):
+                submit(("served", rate), leg_check_served, rate, row["duration_s"],
+                       row["idx"][part].tolist(), row["got"][part].tolist())
+        for op, g in checks.get("batched", {}).items():
+            for a, b in _chunks(len(g), 16):
+                submit(("batched", op), leg_check_segments, op, a, b, g[a:b])
+        if "plain" in checks:
+            for name in ("E1", "E2"):
+                for a, b in _chunks(_LEG["n"], 64):
+                    submit(("plain", name), leg_check_elementwise, name, a, b)
+            for a, b in _chunks(_LEG["n"], 32):
+                submit(("plain", "R"), leg_plain_reduce, a, b)
+        if "dot" in checks:
+            submit(("dot",), leg_check_dot, checks["dot"])
+        parts = {}
+        for key, job in jobs:
+            parts.setdefault(key, []).append(job.get())
+        ok = True
+        if "plain" in checks:
+            p = checks["plain"]
+            out["plain"] = {}
+            for name in ("E1", "E2"):
+                rows = parts[("plain", name)]
+                lanes, bad = sum(r[0] for r in rows), sum(r[1] for r in rows)
+                out["plain"][name] = {"lanes_checked": lanes, "lanes_outside_bound": bad,
+                                      "worst_err_over_bound": max(r[2] for r in rows)}
+                ok &= bad == 0 and lanes == _LEG["n"]
+            rows = parts[("plain", "R")]
+            want = {"R1": sum(r[0] for r in rows), "R2": sum(r[1] for r in rows),
+                    "R3": max(r[2] for r in rows)}
+            for name, w in want.items():
+                same = p[name] == w
+                out["plain"][name] = {"gpu": p[name], "oracle": w, "exact_match": same}
+                ok &= same
+        if "dot" in checks:
+            out["dot_1m"] = parts[("dot",)][0]
+            ok &= out["dot_1m"]["ok"]
+        if "precision" in checks:
+            out["precision"] = {}
+            for (fmt, case) in checks["precision"]:
+                r = parts[("precision", fmt, case)][0]
+                out["precision"].setdefault(fmt, {})[case] = r
+                ok &= r["ok"]
+        if "batched" in checks:
+            out["batched"] = {}
+            for op, g in checks["batched"].items():
+                rows = parts[("batched", op)]
+                bad = sum(r[1] for r in rows)
+                out["batched"][op] = {"segments": len(g), "outside_gate": bad,
+                                      "worst_err_over_gate": max(r[0] for r in rows),
+                                      "gate": "exact" if op == "max" else "2e-6 sum|terms|"}
+                ok &= bad == 0
+        if "served" in checks:
+            out["served"] = {}
+            for rate, row in checks["served"].items():
+                rows = parts[("served", rate)]
+                bad = sum(r[1] for r in rows)
+                out["served"][str(rate)] = {
+                    "jobs_checked": len(row["idx"]), "largest_checked": row["largest"],
+                    "outside_gate": bad, "worst_err_over_gate": max(r[0] for r in rows),
+                    "batched_equals_per_job_bitwise": row["same"], "jobs_compared": row["compared"]}
+                ok &= bad == 0 and row["same"]
+        out["all_ok"] = bool(ok)
+        return out
 
 
 def _time_ms(torch, fn, reps, stream):
@@ -117,17 +422,18 @@ def _time_ms(torch, fn, reps, stream):
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
-def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
+def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000, hits=2000):
     """The host side of the path (front end, code generation, compile cache,
-    launch): the cost of compile(expr, dtypes) when hipRTC
-    runs (cold), when the code object comes from the disk cache (after the
-    in-memory cache is dropped) and when it is in memory (front end, code
-    generation with the symbol's SHA-256, and the lookup), for E1 and for
-    R2's two reduce
-    kernels; then the host time of one elementwise call (argument marshalling
-    and the enqueue) and the GPU time per launch of a 4096-element E1, back to
-    back.  Each cold source is new (its own kernel name) and the disk cache is
-    a fresh directory, so nothing is found by accident."""
+    launch): the cost of compile(expr, dtypes) when hipRTC runs (cold), when
+    the code object comes from the disk cache (after the in-memory caches are
+    dropped), when it is in memory but no handle for the text is held (front
+    end, code generation with the symbol's SHA-256, and the lookup), and when
+    a handle for the same text is still held (the handle cache: one hash
+    lookup and a reference), for E1 and for R2's two reduce kernels; then the
+    host time of one elementwise call (argument marshalling and the enqueue)
+    and the GPU time per launch of a 4096-element E1, back to back.  Each cold
+    source is new (its own kernel name) and the disk cache is a fresh
+    directory, so nothing is found by accident."""
     import shutil
     import tempfile
     binding = hm.hipmr
@@ -140,6 +446,7 @@ def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
         for label, (sig, expr), combine in (("elementwise_E1", workloads.E1, None),
                                             ("reduce_R2", workloads.R_SUM[:2], workloads.R_SUM[2:])):
             times = {"cold": [], "disk": [], "memory": []}
+            handle_us, handle_prep_us = [], []
             before = binding.cache_stats()
             for r in range(reps):
                 name = f"cold{r}_{tag}"
@@ -154,10 +461,25 @@ def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
                     if phase == "disk":
                         binding.cache_drop_memory()
                     t0 = time.perf_counter()
-                    build()
+                    held = build()
                     times[phase].append((time.perf_counter() - t0) * 1e3)
+                # `held` keeps the memory phase's handle alive: compile() of the
+                # same text is now a handle-cache hit
+                t0 = time.perf_counter()
+                for _ in range(hits):
+                    hm.compile(expr, sig, name=name)
+                handle_us.append((time.perf_counter() - t0) / hits * 1e6)
+                if combine:
+                    t0 = time.perf_counter()
+                    for _ in range(hits):
+                        binding.prepare_reduce(hm.compile(expr, sig, name=name), *combine)
+                    handle_prep_us.append((time.perf_counter() - t0) / hits * 1e6)
+                del held
             after = binding.cache_stats()
             res[label] = {f"{p}_ms_median": round(float(np.median(v)), 4) for p, v in times.items()}
+            res[label]["handle_hit_us_median"] = round(float(np.median(handle_us)), 2)
+            if handle_prep_us:
+                res[label]["handle_hit_with_prepare_us_median"] = round(float(np.median(handle_prep_us)), 2)
             res[label]["cache_counts"] = {f: after[f] - before[f]
                                           for f in ("compiles", "disk_hits", "memory_hits")}
     finally:
@@ -193,7 +515,7 @@ def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000):
     return res
 
 
-def bench_dot(torch, hm, workloads, dev, stream, reps=200):
+def bench_dot(torch, hm, workloads, dev, stream, checks, reps=200):
     """The small dot product x . y over 2^20 float32 (8.4 MB, about 1 us of
     HBM traffic): a launch-bound call, reported in microseconds.  `async_us`
     is the per-call time of back-to-back calls (HIP events around all of
@@ -240,6 +562,7 @@ def bench_dot(torch, hm, workloads, dev, stream, reps=200):
     torch.cuda.synchronize()
     same = bool(torch.equal(out, eager))
     graph_ms = _time_ms(torch, lambda: graph.launch(side), 20, side) / 10
+    checks["dot"] = float(eager.item())
     return {"n": int(x.size), "bytes": 8 * int(x.size), "async_us": round(async_us, 2),
             "synced_us_p50": round(float(np.median(synced)), 2),
             "event_us_p50": round(gpu_ms * 1e3, 2),
@@ -285,41 +608,54 @@ def bench_shifted(torch, hm, dev, stream, reps=20):
     return res
 
 
-def bench_precision(torch, hm, workloads, dev, stream, reps=10, copies=4):
-    """Compensated sum and scaled two-pass L2 norm at n = 2**27 per format.
-    `copies` rotated copies of the input (>= 4 x 134-268 MB) keep the working
-    set out of the 256 MB last-level cache."""
+def bench_precision(torch, hm, workloads, dev, stream, checks, reps=10, copies=4):
+    """Compensated sum and scaled two-pass L2 norm at n = 2**27 per format,
+    for the lognormal values and for the cancellation case.  `copies` rotated
+    copies of the input (>= 4 x 134-268 MB) keep the working set out of the
+    256 MB last-level cache.  The results of the last timed calls go to the
+    accuracy checks."""
     n = workloads.N_PRECISION
-    v64 = workloads.precision_values(n, "lognormal")
     out = {}
-    for fmt in ("bfloat16", "float16", "fp8_e4m3"):
-        q = workloads.quantize(fmt, v64)
-        tdt = {"bfloat16": torch.bfloat16, "float16": torch.float16,
-               "fp8_e4m3": torch.float8_e4m3fn}[fmt]
-        host = torch.from_numpy(q.bits)
-        host = host.view(torch.int16 if host.element_size() == 2 else torch.uint8).view(tdt)
-        bufs = [host.to(dev) for _ in range(copies)]
-        k = hm.compile("x[i]", f"float: const {fmt} *x", name=f"bench_{fmt[:4]}")
-        o = torch.empty((), dtype=torch.float64, device=dev)
-        ws = hm.hipmr.workspace(hm.reduce_workspace_bytes(k, n), dev, stream.cuda_stream)
-        it = [0]
+    checks["precision"] = {}
+    for case in ("lognormal", "cancel"):
+        v64 = workloads.precision_values(n, case)
+        for fmt in ("bfloat16", "float16", "fp8_e4m3"):
+            q = workloads.quantize(fmt, v64)
+            tdt = {"bfloat16": torch.bfloat16, "float16": torch.float16,
+                   "fp8_e4m3": torch.float8_e4m3fn}[fmt]
+            host = torch.from_numpy(q.bits)
+            host = host.view(torch.int16 if host.element_size() == 2 else torch.uint8).view(tdt)
+            bufs = [host.to(dev) for _ in range(copies)]
+            k = hm.compile("x[i]", f"float: const {fmt} *x", name=f"bench_{fmt[:4]}")
+            o_sum = torch.empty((), dtype=torch.float64, device=dev)
+            o_nrm = torch.empty((), dtype=torch.float64, device=dev)
+            ws = hm.hipmr.workspace(hm.reduce_workspace_bytes(k, n), dev, stream.cuda_stream)
+            it = [0]
 
-        def nxt():
-            it[0] += 1
-            return bufs[it[0] % copies]
-        inv = 1.0 / q.scale
-        t_sum = _time_ms(torch, lambda: hm.reduce_compensated(k, n, [nxt()], inv, o, ws), reps, stream)
-        sum_symbols = k.last_symbols()
-        t_nrm = _time_ms(torch, lambda: hm.norm2(k, n, [nxt()], inv, 2, o, ws), reps, stream)
-        nbytes = n * host.element_size()
-        out[fmt] = {"sum_ms": round(t_sum, 4), "sum_GB/s": round(nbytes / t_sum / 1e6, 1),
-                    "norm2_ms": round(t_nrm, 4),
-                    "norm2_GB/s": round(2 * nbytes / t_nrm / 1e6, 1),
-                    "sum_symbols": sum_symbols, "norm2_symbols": k.last_symbols()}
-        del bufs
-        torch.cuda.empty_cache()
-    return {"n": n, "workload": "lognormal(0,3) x random sign, per-tensor power-of-two scale",
-            "bytes_note": "sum reads n*size once; the scaled norm reads it twice", "formats": out}
+            def nxt():
+                it[0] += 1
+                return bufs[it[0] % copies]
+            inv = 1.0 / q.scale
+            t_sum = _time_ms(torch, lambda: hm.reduce_compensated(k, n, [nxt()], inv, o_sum, ws),
+                             reps, stream)
+            sum_symbols = k.last_symbols()
+            t_nrm = _time_ms(torch, lambda: hm.norm2(k, n, [nxt()], inv, 2, o_nrm, ws), reps, stream)
+            nbytes = n * host.element_size()
+            checks["precision"][(fmt, case)] = (float(o_sum.item()), float(o_nrm.item()))
+            out.setdefault(case, {})[fmt] = {
+                "sum_ms": round(t_sum, 4), "sum_GB/s": round(nbytes / t_sum / 1e6, 1),
+                "sum_frac_of_peak": round(nbytes / t_sum / 1e6 / HBM_PEAK_GBS, 4),
+                "norm2_ms": round(t_nrm, 4), "norm2_GB/s": round(2 * nbytes / t_nrm / 1e6, 1),
+                "norm2_frac_of_peak": round(2 * nbytes / t_nrm / 1e6 / HBM_PEAK_GBS, 4),
+                "sum_symbols": sum_symbols, "norm2_symbols": k.last_symbols()}
+            del bufs
+            torch.cuda.empty_cache()
+        del v64
+    return {"n": n, "workload": "lognormal(0,3) x random sign, and the cancellation case "
+                                "[x; -x (1 + eps)]; per-tensor power-of-two scale",
+            "bytes_note": "sum reads n*size once; the scaled norm reads it twice",
+            "inputs": f"{copies} rotated copies (out of the 256 MB last-level cache)",
+            "cases": out}
 
 
 def bench_scan(torch, hm, workloads, dev, stream, reps=10):
@@ -456,20 +792,30 @@ def bench_complex(torch, hm, workloads, dev, stream, reps=10):
     return res
 
 
-def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
+def bench_batched(torch, hm, workloads, dev, checks, reps=12, baseline_reps=2, copies=3):
     """4096 lognormal segments (62,032,791 float32): segmented sum, max and dot
-    as one graph replay of the persistent launch sequences, against one plain
-    launch pair per segment (eager, and captured in a graph)."""
+    (three persistent launch sequences) replayed from HIP graphs, against one
+    plain launch pair per segment (eager, and captured in a graph).  The
+    batched graphs run the three ops on three streams (fork / join inside the
+    graph, so one op's planner and fold overlap the others' tile kernels) and,
+    for reference, one after the other on one stream.  Every op of every
+    replay reads arrays of its own: `copies` rotated sets of one x per op and
+    one y (12 x 0.25 GB, far beyond the 256 MB last-level cache), one graph
+    per set, so no op reads what another just read and the inputs come from
+    HBM."""
     offsets, x, y = workloads.segments()
     nseg = len(offsets) - 1
     total = int(offsets[-1])
     od = torch.from_numpy(offsets).to(dev)
-    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
     ops = {"sum": ("x[i]", "a+b", "0", 4), "max": ("x[i]", "max(a,b)", "-INFINITY", 4),
            "dot": ("x[i]*y[i]", "a+b", "0", 8)}
+    xh, yh = torch.from_numpy(x), torch.from_numpy(y)
+    sets = [({op: xh.to(dev) for op in ops}, yh.to(dev)) for _ in range(copies)]
+    xd, yd = sets[0][0]["sum"], sets[0][1]
     sig = "float: const float *x, const float *y"
     ks = {op: hm.compile(m, sig, name=f"batch_{op}") for op, (m, _, _, _) in ops.items()}
     stream = torch.cuda.Stream()
+    side = {"max": torch.cuda.Stream(), "dot": torch.cuda.Stream()}
     res = {}
     with torch.cuda.stream(stream):
         outs = {op: torch.empty(nseg, device=dev) for op in ops}
@@ -480,17 +826,52 @@ def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
             tuned[op] = hm.autotune_segmented(ks[op], comb, neu, od, total, [xd, yd], outs[op],
                                               reps=3, workspace_buf=wss[op], stream=stream)
 
-        def issue():
-            for op, (m, comb, neu, _) in ops.items():
-                hm.reduce_segmented(ks[op], comb, neu, od, total, [xd, yd], outs[op],
-                                    workspace_buf=wss[op], stream=stream)
-        issue()
-        stream.synchronize()
-        graph = hm.Graph()
-        with graph.capture(stream):
-            issue()
-        t_batched = _time_ms(torch, lambda: graph.launch(stream), reps, stream)
-        t_eager_batched = _time_ms(torch, issue, reps, stream)
+        def one(op, c, st):
+            m, comb, neu, _ = ops[op]
+            xs, ys = sets[c]
+            hm.reduce_segmented(ks[op], comb, neu, od, total, [xs[op], ys], outs[op],
+                                workspace_buf=wss[op], stream=st, config={"flags": hm.CFG_TUNED})
+
+        def issue_serial(c=0):
+            for op in ops:
+                one(op, c, stream)
+
+        def issue_concurrent(c=0):
+            fork = torch.cuda.Event()
+            fork.record(stream)
+            for op, st in side.items():
+                st.wait_event(fork)
+                one(op, c, st)
+            one("sum", c, stream)
+            for st in side.values():
+                join = torch.cuda.Event()
+                join.record(st)
+                stream.wait_event(join)
+        issue_serial()
+        issue_concurrent()
+        torch.cuda.synchronize()
+        graphs = {"concurrent": [], "serial": []}
+        for c in range(copies):
+            for kind, fn in (("concurrent", issue_concurrent), ("serial", issue_serial)):
+                g = hm.Graph()
+                with g.capture(stream):
+                    fn(c)
+                graphs[kind].append(g)
+        it = [0]
+
+        def replay(kind):
+            it[0] += 1
+            graphs[kind][it[0] % copies].launch(stream)
+
+        def eager():
+            it[0] += 1
+            issue_serial(it[0] % copies)
+        t_batched = _time_ms(torch, lambda: replay("concurrent"), reps, stream)
+        t_serial = _time_ms(torch, lambda: replay("serial"), reps, stream)
+        t_eager_batched = _time_ms(torch, eager, reps, stream)
+        torch.cuda.synchronize()
+        checks["batched"] = {op: outs[op].cpu().numpy().astype(np.float64) for op in ops}
+        symbols = {op: ks[op].last_symbols() for op in ops}
         # baseline: one plain map-reduce (two launches) per segment and op
         plain_out = torch.empty(nseg, device=dev)
         ws1 = hm.hipmr.workspace(hm.reduce_workspace_bytes(ks["sum"], 1), dev, stream.cuda_stream)
@@ -509,31 +890,52 @@ def bench_batched(torch, hm, workloads, dev, reps=10, baseline_reps=2):
         t_plain_graph = _time_ms(torch, lambda: pgraph.launch(stream), baseline_reps, stream)
     nbytes = sum(total * b for (_, _, _, b) in ops.values())
     res = {"nseg": nseg, "total_elements": total, "algorithmic_bytes": nbytes,
+           "inputs": f"{copies} rotated sets of one x per op and one y (each op reads its own "
+                     f"arrays; out of the 256 MB last-level cache)",
            "batched_graph_ms": round(t_batched, 4),
            "batched_graph_GB/s": round(nbytes / t_batched / 1e6, 1),
+           "batched_graph_frac_of_peak": round(nbytes / t_batched / 1e6 / HBM_PEAK_GBS, 4),
+           "batched_graph_note": "the three ops on three streams inside one graph",
+           "serial_graph_ms": round(t_serial, 4),
+           "serial_graph_GB/s": round(nbytes / t_serial / 1e6, 1),
            "batched_eager_ms": round(t_eager_batched, 4),
            "per_segment_eager_ms": round(t_plain, 3),
            "per_segment_graph_ms": round(t_plain_graph, 3),
            "speedup_vs_per_segment": round(t_plain / t_batched, 1),
            "speedup_vs_per_segment_graph": round(t_plain_graph / t_batched, 1),
-           "launches_batched": 3 * 3, "launches_per_segment": 3 * nseg * 2,
-           "tuned": tuned}
+           "launches_batched": sum(len(v) for v in symbols.values()),
+           "launches_per_segment": 3 * nseg * 2,
+           "symbols": symbols, "tuned": tuned}
+    del sets
+    torch.cuda.empty_cache()
     return res
 
 
-def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates=None):
+SERVE_MODES = (("resident", dict(resident=1)),
+               ("batched", dict(nstreams=4, max_batch_jobs=1024)),
+               ("per_job", dict(nstreams=4, max_batch_jobs=1)))
+
+
+def bench_serving(torch, hm, workloads, dev, checks, duration_s=4.0, warmup_s=1.0, rates=None,
+                  checked_jobs=200, largest_jobs=20):
     """Poisson streams at 2k, 10k and 50k jobs/s (8 templates, float32 /
     bfloat16 50/50, n log-uniform over [2^10, 2^24], slices of a resident 2^24
     pool), plus a 200k jobs/s stress rate beyond them, replayed open-loop
-    through the continuous-batching loop and through the one-launch-pair-per-
-    job baseline on the same 4 streams; latency = scheduled arrival -> the
-    loop sees the job's completion flag (result in device memory)."""
+    through three forms of the serving loop with a 64 GiB budget: the
+    resident kernel fed from a descriptor ring (`resident`, the served form),
+    batches launched on 4 streams (`batched`), and one launch pair per job on
+    the same 4 streams (`per_job`, the baseline); latency = scheduled arrival
+    -> the loop sees the job's completion flag (result in device memory).
+    Per configured rate, the resident results of `checked_jobs` measured jobs
+    (the `largest_jobs` largest among them) go to the accuracy checks, and
+    every job's result is compared bit for bit across the three forms."""
     f32, bf16 = workloads.serving_pool()
     dev_f32 = {k: torch.from_numpy(v).to(dev) for k, v in f32.items()}
     dev_bf16 = {k: torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).to(dev)
                 for k, v in bf16.items()}
     res = {"pool": workloads.N_POOL, "duration_s": duration_s, "warmup_s": warmup_s,
-           "budget_bytes": 64 << 30, "nstreams": 4, "rates": {}}
+           "budget_bytes": 64 << 30, "served_form": "resident", "baseline": "per_job",
+           "rates": {}}
     for rate in rates or (*workloads.SERVING_RATES, 200000):
         sched = workloads.serving_schedule(rate, warmup_s + duration_s)
         m = len(sched["n"])
@@ -542,12 +944,13 @@ def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates
         job_bytes = sched["n"] * es * arrays
         out = torch.empty(m, dtype=torch.float64, device=dev)
         row = {"jobs": int(m)}
+        results = {}
         if rate not in workloads.SERVING_RATES:
             row["note"] = "stress rate beyond the configured ones"
-        for mode, max_jobs in (("batched", 1024), ("per_job", 1)):
-            server = hm.Server(hbm_budget_bytes=64 << 30, nstreams=4, max_batch_jobs=max_jobs)
+        for mode, kw in SERVE_MODES:
+            server = hm.Server(hbm_budget_bytes=64 << 30, **kw)
             jobs = server.jobs(m)
-            for key, src in (("x", None), ("y", None), ("w", None)):
+            for key in ("x", "y", "w"):
                 base_f = dev_f32[key].data_ptr()
                 base_b = dev_bf16[key].data_ptr()
                 jobs[key] = np.where(sched["bf16"], base_b + sched["offset"] * 2,
@@ -558,8 +961,12 @@ def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates
             jobs["arrival_ns"] = sched["arrival_ns"]
             jobs["out"] = out.data_ptr() + 8 * np.arange(m, dtype=np.uint64)
             jobs["a"], jobs["b"] = 2.5, -0.5
+            out.fill_(float("nan"))
+            torch.cuda.synchronize()
             done = server.run_schedule(jobs)
             server.close()
+            torch.cuda.synchronize()
+            results[mode] = out.cpu().numpy().copy()
             meas = sched["arrival_ns"] >= int(warmup_s * 1e9)
             lat = (done["done_ns"] - done["arrival_ns"])[meas] / 1e3
             first = int(np.min(done["arrival_ns"][meas]))
@@ -574,10 +981,25 @@ def bench_serving(torch, hm, workloads, dev, duration_s=5.0, warmup_s=1.0, rates
                          "GB/s": round(float(job_bytes[meas].sum()) / span / 1e9, 2),
                          "queue_p50_us": round(float(np.percentile(queue, 50)), 1),
                          "service_p50_us": round(float(np.percentile(service, 50)), 1),
-                         "mean_batch_jobs": round(float(np.mean(done["batch_jobs"][meas])), 2),
+                         "mean_jobs_together": round(float(np.mean(done["batch_jobs"][meas])), 2),
                          "status_ok": bool(np.all(done["status"] == 0))}
-        row["p99_speedup"] = round(row["per_job"]["p99_us"] / row["batched"]["p99_us"], 2)
-        row["p50_speedup"] = round(row["per_job"]["p50_us"] / row["batched"]["p50_us"], 2)
+        if rate in workloads.SERVING_RATES:
+            meas_idx = np.nonzero(sched["arrival_ns"] >= int(warmup_s * 1e9))[0]
+            by_size = meas_idx[np.argsort(sched["n"][meas_idx], kind="stable")]
+            largest = by_size[-largest_jobs:]
+            rng = np.random.default_rng(rate)
+            rest = np.setdiff1d(meas_idx, largest)
+            idx = np.sort(np.concatenate([largest, rng.choice(rest, checked_jobs - largest_jobs,
+                                                              replace=False)]))
+            r, b, p = results["resident"], results["batched"], results["per_job"]
+            checks.setdefault("served", {})[rate] = {
+                "duration_s": warmup_s + duration_s, "idx": idx, "got": r[idx],
+                "largest": int(largest.size), "compared": int(m),
+                "same": bool(np.array_equal(r.view(np.uint64), p.view(np.uint64)) and
+                             np.array_equal(b.view(np.uint64), p.view(np.uint64)))}
+        for mode in ("resident", "batched"):
+            row[f"{mode}_p99_speedup"] = round(row["per_job"]["p99_us"] / row[mode]["p99_us"], 2)
+            row[f"{mode}_p50_speedup"] = round(row["per_job"]["p50_us"] / row[mode]["p50_us"], 2)
         res["rates"][str(rate)] = row
         print(f"serving {rate}/s done", file=sys.stderr, flush=True)
     return res
@@ -590,16 +1012,21 @@ def main():
               "would shard across GPUs is described, not measured", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
-    import paper_1304_5553_amd as hm
     import workloads
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     n = args.n
     x, y = workloads.plain_xy(n)
     k = workloads.plain_k(n)
+    # the CPU leg's worker processes are forked here, before the GPU is touched
+    leg = None if args.no_cpu_baseline else CpuLeg(x, y, k, n)
+    checks = {}
+
+    import torch
+
+    import paper_1304_5553_amd as hm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     xd = torch.from_numpy(x).to(dev)
     yd = torch.from_numpy(y).to(dev)
     kd = torch.from_numpy(k).to(dev)
@@ -691,7 +1118,8 @@ def main():
     dom_symbol = last[dominant].last_symbols()[0]
     traffic = counter_traffic(dom_symbol)
 
-    # results of the last step (sanity: exact integer results are printed)
+    # results of the last step, and the elementwise outputs of one more pass
+    # each, for the accuracy checks
     result = {}
     if "R1" in ops:
         result["R1_count"] = int(outs["count"].item())
@@ -699,6 +1127,12 @@ def main():
         result["R2_sum"] = int(outs["sum"].item())
     if "R3" in ops:
         result["R3_max"] = float(outs["max"].item())
+    if leg is not None and {"E1", "E2", "R1", "R2", "R3"} <= set(ops):
+        for name in ("E1", "E2"):
+            run_op(name, last)
+            torch.cuda.synchronize()
+            torch.from_numpy(_LEG["z"][name]).copy_(z)
+        checks["plain"] = {"R1": result["R1_count"], "R2": result["R2_sum"], "R3": result["R3_max"]}
 
     line = {
         "metric": METRIC,
@@ -736,13 +1170,13 @@ def main():
         line["compile"] = bench_compile(torch, hm, workloads, dev, stream)
         print("compile done", file=sys.stderr, flush=True)
     if "dot" in ext:
-        line["dot"] = bench_dot(torch, hm, workloads, dev, stream)
+        line["dot"] = bench_dot(torch, hm, workloads, dev, stream, checks)
         print("dot done", file=sys.stderr, flush=True)
     if "precision" in ext:
-        line["precision"] = bench_precision(torch, hm, workloads, dev, stream)
+        line["precision"] = bench_precision(torch, hm, workloads, dev, stream, checks)
         print("precision done", file=sys.stderr, flush=True)
     if "batched" in ext:
-        line["batched"] = bench_batched(torch, hm, workloads, dev)
+        line["batched"] = bench_batched(torch, hm, workloads, dev, checks)
         print("batched done", file=sys.stderr, flush=True)
     if "shifted" in ext:
         line["shifted"] = bench_shifted(torch, hm, dev, stream)
@@ -761,10 +1195,20 @@ def main():
         print("cg done", file=sys.stderr, flush=True)
     if "served" in ext:
         rates = tuple(int(r) for r in args.serving_rates.split(",") if r.strip()) or None
-        line["served"] = bench_serving(torch, hm, workloads, dev, duration_s=args.serving_duration,
-                                       rates=rates)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(x, y, k, args.cpu_sample)
+        line["served"] = bench_serving(torch, hm, workloads, dev, checks,
+                                       duration_s=args.serving_duration, rates=rates)
+    if leg is not None:
+        try:
+            line["cpu_baseline"] = leg.baseline(args.cpu_sample_one, args.cpu_sample)
+            print("cpu baseline done", file=sys.stderr, flush=True)
+            if not args.no_accuracy:
+                line["accuracy"] = leg.accuracy(checks)
+                print("accuracy done", file=sys.stderr, flush=True)
+                if not line["accuracy"]["all_ok"]:
+                    print("bench.py: a timed result is outside its gate against the oracle",
+                          file=sys.stderr, flush=True)
+        finally:
+            leg.close()
     print(json.dumps(line), flush=True)
 
 

@@ -436,15 +436,22 @@ typedef struct hipmr_server_config {
     int32_t batch_backlog;       /* jobs are packed together only while more than this many wait
                                     per free stream (a shorter queue runs one job per stream, as
                                     the one-launch-pair-per-job loop does); 0: 8                   */
-    int32_t reserved;            /* 0                                                               */
+    int32_t resident;            /* 0: batches launched on the streams (above); 1: one resident
+                                    kernel takes the jobs from a descriptor ring in mapped host
+                                    memory, no launch per job (nstreams, max_batch_jobs,
+                                    max_batch_bytes, solo_bytes and batch_backlog unused;
+                                    max_batch_tiles sizes its ring of tile partials, rounded up
+                                    to a power of two >= 8192; blocks_per_cu: blocks of 1024
+                                    threads per CU, 0: 1)                                          */
 } hipmr_server_config;
 
 typedef struct hipmr_completion {
     uint64_t ticket;         /* submit: its ticket; run_schedule: the job's index                */
     int32_t status;          /* HIPMR_OK, or the code the job was rejected with                  */
-    int32_t batch_jobs;      /* jobs in the batch that carried it                                */
+    int32_t batch_jobs;      /* jobs in the batch that carried it (resident mode: jobs on the
+                                device, itself included, when it was handed over)              */
     int64_t arrival_ns;      /* run_schedule: relative to the call; submit: server clock         */
-    int64_t launch_ns;       /* when its batch was launched                                      */
+    int64_t launch_ns;       /* when its batch was launched (resident: handed to the ring)       */
     int64_t done_ns;         /* when the loop saw the batch complete (result visible on the host) */
 } hipmr_completion;
 
@@ -470,12 +477,27 @@ size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
  *     dtype) and one block per job folding its tiles in a fixed order.  A job
  *     of at most 16 tiles alone runs in one launch (one block computes and
  *     folds its tiles) unless max_batch_jobs is 1.
- * A job's tiles depend only on the job, so its result is bitwise the same
- * alone or in any mix.
+ * With cfg->resident = 1 no kernel is launched per job: admitted jobs go, in
+ * arrival order, into a ring of descriptors in mapped host memory, and one
+ * resident kernel (on a stream of its own) takes them as they are published:
+ * a dispatcher wave copies each descriptor to the device and publishes its
+ * tiles; the other blocks take tile tickets in order, and the wave completing
+ * a job's last tile group folds the job and writes its flag.  Admission also
+ * waits while the ring (4096 jobs) or the ring of tile partials is full.  An
+ * instance runs at most 2 s (every wait in it is bounded by that deadline);
+ * the loop replaces it every 250 ms and stops it after 10 ms without jobs,
+ * so a device-wide synchronisation returns once the server is idle.  Jobs
+ * an instance could not finish by its deadline complete with E_HIP.
+ * On every path a job's tiles depend only on the job, and its tile partials
+ * are folded in a fixed order (64-tile groups, then the groups), so its
+ * result is bitwise the same alone, in any mix and on any path.  A job has at
+ * most 8192 tiles (2^26 float32 / 2^27 bfloat16 elements; E_UNSUPPORTED
+ * beyond).
  * Completion is observed through per-job flags in mapped host memory that the
- * folding block writes after the result (a stream query is the watchdog for
- * errors).  Inputs stay resident: jobs name device arrays.  The server
- * allocates pinned host memory for descriptors and flags (not device memory).
+ * folding wave or block writes after the result (a stream query is the
+ * watchdog for errors).  Inputs stay resident: jobs name device arrays.  The
+ * server allocates pinned host memory for descriptors and flags (not device
+ * memory).
  * Errors: E_INVALID (config), E_WORKSPACE, E_COMPILE, E_HIP. */
 hipmr_status hipmr_server_create(const hipmr_server_config *cfg, void *workspace,
                                  size_t workspace_bytes, hipmr_server_t *out);

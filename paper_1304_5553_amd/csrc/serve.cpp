@@ -52,6 +52,13 @@ constexpr int kInlineJobs = 24;          // descriptors passed as kernel argumen
 constexpr int kMaxSkipped = 64;          // large jobs one batch of small ones may be packed past
 constexpr int kOneLaunchTiles = 16;      // a job of at most this many tiles alone: one launch
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
+constexpr int kMaxJobTiles = 8192;       // tiles of one job (its fold has at most 128 groups)
+constexpr int kRing = 4096;               // resident: job descriptors in flight (power of two)
+constexpr size_t kCtrlBytes = 4096;       // resident: control words (zeroed before each launch)
+constexpr int64_t kRotateNs = 250000000;  // resident: a new instance every 250 ms of service
+constexpr int64_t kIdleStopNs = 10000000; // resident: the instance stops after 10 ms without jobs
+constexpr double kLifeS = 2.0;            // resident: an instance's deadline (it exits by then)
+constexpr int kEpochShift = 44;           // resident: stop / exit words = epoch << 44 | job index
 
 // Device descriptor of one job (64 bytes; the layout matches the device-side
 // hipmr_sjob struct in the kernels below).
@@ -110,7 +117,8 @@ __device__ __forceinline__ float2 hipmr_job_comb2(float2 a, float2 b) {
 // elements (all arrays 16-byte aligned after them; 0 when they share no
 // alignment), then tiles of `tt` elements = P passes of 64 lanes x 4 chunks x
 // V elements.  P (1, 2, 4 or 8) is the smallest that keeps the job at or
-// under 8192 tiles; arrays without a common alignment use P = 1.
+// under 8192 tiles (jobs that need more are refused when submitted); arrays
+// without a common alignment take their tiles element by element.
 struct hipmr_geom { long long ab, tt; int passes, tiles; };
 
 __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
@@ -119,7 +127,7 @@ __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
   g.ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
   const long long body = J.n - g.ab;
   int p = 1;
-  while (J.head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
+  while (p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
   g.passes = p;
   g.tt = tt0 * p;
   const long long t = (body + g.tt - 1) / g.tt;
@@ -224,58 +232,91 @@ __device__ __forceinline__ float2 hipmr_job_dispatch(const hipmr_sjob& J, long l
   }
 }
 
-// Final fold of one job's tile partials [t0, t1) by one block of 1024
-// threads (FP64): thread k folds tiles t0 + k, t0 + k + 1024, ... in order
-// (eight loads in flight, so one round covers 8192 tiles), then the wave
-// butterfly, then the 16 waves in order; thread 0 finishes the job (sqrt,
-// ratio).
+// Final fold of one job's tile partials, the same arithmetic on every path
+// (launched batches, one launch per job, the resident kernel), so a job's
+// result never depends on the path that ran it.  FP64, in two levels:
+//   1. group g of 64 consecutive tiles: lane l holds partial 64 g + l (the
+//      neutral element past the job's last tile), then the wave butterfly;
+//   2. the groups (at most 128, as a job has at most 8192 tiles): lane l
+//      folds the neutral element, group l and group l + 64 in that order,
+//      then the wave butterfly.
+// Every lane ends with the same value.  The second component (the weight of
+// the weighted mean, 0 otherwise) always sums.
+__device__ __forceinline__ double2 hipmr_fin_comb(bool mx, double2 a, double2 b) {
+  return make_double2(mx ? __builtin_elementwise_maximum(a.x, b.x) : a.x + b.x, a.y + b.y);
+}
+
+__device__ __forceinline__ double2 hipmr_fin_wave(bool mx, double2 v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1)
+    v = hipmr_fin_comb(mx, v, make_double2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)));
+  return v;
+}
+
+__device__ __forceinline__ double2 hipmr_fin_neutral(bool mx) {
+  return make_double2(mx ? -__builtin_huge_val() : 0.0, 0.0);
+}
+
+// Level 1: group g of a job whose partial k sits at tpart[(base + k) & mask].
+__device__ __forceinline__ double2 hipmr_fin_group(bool mx, const float2* tpart, unsigned long long base,
+                                                   unsigned long long mask, int g, int ntiles, int lane) {
+  const int k = 64 * g + lane;
+  double2 v = hipmr_fin_neutral(mx);
+  if (k < ntiles) {
+    const float2 p = tpart[(base + (unsigned long long)k) & mask];
+    v = make_double2((double)p.x, (double)p.y);
+  }
+  return hipmr_fin_wave(mx, v);
+}
+
+// Level 2: lane l holds group l (if h0) and group l + 64 (if h1).
+__device__ __forceinline__ double2 hipmr_fin_level2(bool mx, bool h0, double2 v0, bool h1, double2 v1) {
+  double2 a = hipmr_fin_neutral(mx);
+  if (h0) a = hipmr_fin_comb(mx, a, v0);
+  if (h1) a = hipmr_fin_comb(mx, a, v1);
+  return hipmr_fin_wave(mx, a);
+}
+
+// Level 2 over the ng group values gv[0 .. ng).
+__device__ __forceinline__ double2 hipmr_fin_groups(bool mx, const double2* gv, int ng, int lane) {
+  const bool h0 = lane < ng, h1 = lane + 64 < ng;
+  const double2 z = make_double2(0.0, 0.0);
+  return hipmr_fin_level2(mx, h0, h0 ? gv[lane] : z, h1, h1 ? gv[lane + 64] : z);
+}
+
+// The job's result from its total (square root of the norm, ratio of the
+// weighted mean), written before the job's completion flag (in host memory)
+// changes.
+__device__ __forceinline__ void hipmr_job_post(const hipmr_sjob& J, double2 tot,
+                                               unsigned long long* flag, unsigned long long seq) {
+  double r = tot.x;
+  if (J.tmpl == 2) r = sqrt(r);
+  else if (J.tmpl == 7) r = r / tot.y;
+  *J.out = r;
+  // the result is visible system-wide before the completion flag changes
+  __threadfence_system();
+  *(volatile unsigned long long*)flag = seq;
+}
+
+// The fold of the partials [t0, t1) by one block of 1024 threads: wave w
+// takes groups w, w + 16, ...; wave 0 then folds the groups and finishes.
 constexpr int HIPMR_FIN_BLOCK = 1024;
 
 __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, int t1,
                                                  const float2* __restrict__ tpart,
                                                  unsigned long long* flag, unsigned long long seq) {
-  constexpr int NW = HIPMR_FIN_BLOCK / 64;
-  __shared__ double hipmr_fin[2][NW];
+  __shared__ double2 hipmr_gv[128];
   const bool mx = J.tmpl == 3;
-  double a0 = mx ? -__builtin_huge_val() : 0.0, a1 = 0.0;
-  for (int t = t0 + (int)threadIdx.x; t < t1; t += HIPMR_FIN_BLOCK * 8) {
-    float2 p[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (t + HIPMR_FIN_BLOCK * k < t1) p[k] = tpart[t + HIPMR_FIN_BLOCK * k];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (t + HIPMR_FIN_BLOCK * k < t1) {
-        a0 = mx ? __builtin_elementwise_maximum(a0, (double)p[k].x) : a0 + (double)p[k].x;
-        a1 += (double)p[k].y;
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    const double o0 = __shfl_xor(a0, m, 64), o1 = __shfl_xor(a1, m, 64);
-    a0 = mx ? __builtin_elementwise_maximum(a0, o0) : a0 + o0;
-    a1 += o1;
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    hipmr_fin[0][w] = a0;
-    hipmr_fin[1][w] = a1;
+  const int ntiles = t1 - t0, ng = (ntiles + 63) / 64;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int g = w; g < ng; g += HIPMR_FIN_BLOCK / 64) {
+    const double2 v = hipmr_fin_group(mx, tpart, (unsigned long long)t0, ~0ull, g, ntiles, lane);
+    if (lane == 0) hipmr_gv[g] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = hipmr_fin[0][0], q = hipmr_fin[1][0];
-    for (int k = 1; k < NW; ++k) {
-      r = mx ? __builtin_elementwise_maximum(r, hipmr_fin[0][k]) : r + hipmr_fin[0][k];
-      q += hipmr_fin[1][k];
-    }
-    if (J.tmpl == 2) r = sqrt(r);
-    else if (J.tmpl == 7) r = r / q;
-    *J.out = r;
-    // the result is visible system-wide before the job's completion flag (in
-    // host memory) changes
-    __threadfence_system();
-    *(volatile unsigned long long*)flag = seq;
+  if (w == 0) {
+    const double2 tot = hipmr_fin_groups(mx, hipmr_gv, ng, lane);
+    if (lane == 0) hipmr_job_post(J, tot, flag, seq);
   }
 }
 
@@ -383,6 +424,226 @@ extern "C" __global__ void __launch_bounds__(1024)
 {
   hipmr_job_finish(J, 0, hipmr_job_geom(J).tiles, tpart, flags, seq);
 }
+
+// ---------------------------------------------------------------- resident
+// One kernel that stays on the device and takes jobs from a ring of
+// descriptors in mapped host memory, so a job costs no launch.
+//   Host ring (mapped host memory): hdr[0] = jobs published (job s sits in
+//   slot s % R of hr_jobs, its first tile's global index in hr_tstart);
+//   hdr[16] = epoch << 44 | the job index at which instance `epoch` stops
+//   accepting (a word naming another epoch does not stop this one); the
+//   dispatcher writes hdr[32] = epoch << 44 | (jobs accepted + 1) as it
+//   exits; hr_flags[slot] = s + 1 once job s's result is in device memory.
+//   Control words (device memory, zeroed before each launch): ctrl[0] tile
+//   tickets taken; ctrl[16] jobs completed; eight replicas (one line each,
+//   ctrl[32 + 16 r]) of {published: jobs (relative to job_base) << 40 | tiles
+//   (relative to tile_base), in one word so the two always agree; stop}.
+// Block 0, wave 0 is the dispatcher: it copies newly published descriptors
+// into the device ring and publishes them; once the host's stop index is
+// reached and every accepted job has completed (or at its deadline), it sets
+// the stop flag and exits.  Blocks 1.. are workers: thread 0 takes 16
+// consecutive tile tickets (one per wave) and polls the block's replica until
+// they are published; each wave reduces its tile with the tile kernels'
+// arithmetic; the wave completing a 64-tile group folds it, and the wave
+// completing the job's last group folds the groups and writes the result
+// (the fold of every other path).  Every wait is bounded: workers exit on the
+// stop flag, and every wave at the instance's deadline.
+#define HIPMR_RING @@RING@@
+
+__device__ __forceinline__ unsigned long long hipmr_ld_agent(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void hipmr_st_agent(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long hipmr_ld_sys(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ int hipmr_job_ntiles(const hipmr_sjob& J) {
+  const int t = hipmr_job_geom(J).tiles;
+  return t < 1 ? 1 : t;                 // an empty job still has one (empty) tile
+}
+
+#define HIPMR_PUB_TILES(v) ((v) & ((1ull << 40) - 1))
+#define HIPMR_MAX_POLLS (1ull << 25)   // polls per wait, whatever the clock says
+#define HIPMR_PUB_JOBS(v) ((v) >> 40)
+
+__device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __restrict__ hr_jobs,
+                                   const unsigned long long* __restrict__ hr_tstart,
+                                   unsigned long long* ctrl, hipmr_sjob* dring,
+                                   unsigned long long* dtstart, unsigned long long job_base,
+                                   unsigned long long tile_base, unsigned long long epoch,
+                                   unsigned long long deadline) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long t0 = wall_clock64();
+  unsigned long long seq = job_base, stop_at = ~0ull;
+  bool closing = false;
+  // a second bound besides the clock: every pass takes at least one read of
+  // host memory (about a microsecond)
+  for (unsigned long long iter = 0;; ++iter) {
+    if (!closing) {
+      const unsigned long long P = hipmr_ld_sys(hdr);
+      const unsigned long long Sw = hipmr_ld_sys(hdr + 16);
+      // the stop word names the instance it is for (epoch << 44 | job index)
+      const unsigned long long S = (Sw >> 44) == (epoch & ((1ull << 20) - 1)) ? (Sw & ((1ull << 44) - 1))
+                                                                             : ~0ull;
+      const unsigned long long lim = P < S ? P : S;
+      if (lim > seq) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: the host's descriptors
+        const int cnt = lim - seq < 64 ? (int)(lim - seq) : 64;
+        unsigned long long tend = 0;
+        if (lane < cnt) {
+          const unsigned long long s = seq + lane, slot = s & (HIPMR_RING - 1);
+          const hipmr_sjob J = hr_jobs[slot];
+          const unsigned long long ts = hr_tstart[slot];
+          dring[slot] = J;
+          hipmr_st_agent(dtstart + slot, ts);
+          tend = ts + (unsigned long long)hipmr_job_ntiles(J);
+        }
+        tend = __shfl(tend, cnt - 1, 64);
+        seq += cnt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane < 8)
+          hipmr_st_agent(ctrl + 32 + 16 * lane, ((seq - job_base) << 40) | (tend - tile_base));
+        continue;
+      }
+      if (S <= seq) {
+        closing = true;
+        stop_at = seq;
+      }
+    }
+    const bool drained = closing && hipmr_ld_agent(ctrl + 16) == stop_at - job_base;
+    if (drained || wall_clock64() - t0 > deadline || iter > HIPMR_MAX_POLLS) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane < 8) hipmr_st_agent(ctrl + 32 + 16 * lane + 2, 1);
+      if (lane == 0)
+        __hip_atomic_store(hdr + 32, (epoch << 44) | (seq + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+extern "C" __global__ void __launch_bounds__(1024)
+@@PREFIX@@_res(unsigned long long* hdr, const hipmr_sjob* __restrict__ hr_jobs,
+               const unsigned long long* __restrict__ hr_tstart, unsigned long long* hr_flags,
+               unsigned long long* ctrl, hipmr_sjob* dring, unsigned long long* dtstart,
+               unsigned int* gdone, unsigned int* jdone, double2* gpart, float2* tpart,
+               unsigned long long tp_mask, unsigned long long job_base, unsigned long long tile_base,
+               unsigned long long epoch, unsigned long long deadline)
+{
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64)
+      hipmr_res_dispatch(hdr, hr_jobs, hr_tstart, ctrl, dring, dtstart, job_base, tile_base, epoch,
+                         deadline);
+    return;
+  }
+  __shared__ unsigned long long sh_t0, sh_pub, sh_jobs;
+  __shared__ int sh_stop;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
+  const unsigned long long start = wall_clock64();
+  unsigned long long hint = job_base;       // no tile of this wave lies in an earlier job
+  while (true) {
+    if (threadIdx.x == 0)
+      sh_t0 = __hip_atomic_fetch_add(ctrl, 16ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long t0 = sh_t0;
+    unsigned long long done = t0;           // tickets [t0, done) are handled
+    while (done < t0 + 16) {
+      if (threadIdx.x == 0) {
+        unsigned long long v;
+        for (unsigned long long iter = 0;; ++iter) {
+          v = hipmr_ld_agent(rep);
+          if (HIPMR_PUB_TILES(v) > done) break;
+          if (hipmr_ld_agent(rep + 2) != 0 || wall_clock64() - start > deadline + deadline / 8 ||
+              iter > HIPMR_MAX_POLLS)
+            break;
+          __builtin_amdgcn_s_sleep(8);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sh_pub = HIPMR_PUB_TILES(v);
+        sh_jobs = job_base + HIPMR_PUB_JOBS(v);
+        sh_stop = HIPMR_PUB_TILES(v) <= done;   // stopped (or past the deadline) with nothing new
+      }
+      __syncthreads();
+      if (sh_stop) return;                  // every published tile was completed before the stop
+      const unsigned long long pub = sh_pub, njobs = sh_jobs;
+      const unsigned long long avail = pub < t0 + 16 ? pub : t0 + 16;
+      const unsigned long long T = t0 + w;
+      if (T >= done && T < avail) {
+        const unsigned long long G = tile_base + T, fresh = tile_base + pub;
+        // the job holding tile G: the last s in [lo, njobs) whose first tile is <= G.  Slots of
+        // completed jobs below it may already hold jobs published later, whose first tiles are
+        // >= fresh: they count as <= G, which keeps the predicate monotone.
+        unsigned long long lo = hint;
+        if (njobs > HIPMR_RING && njobs - HIPMR_RING > lo) lo = njobs - HIPMR_RING;
+        unsigned long long hi = njobs - 1;
+        while (lo < hi) {
+          const unsigned long long step = (hi - lo + 64) / 64;
+          const unsigned long long cand = lo + (unsigned long long)lane * step;
+          bool pred = false;
+          if (cand <= hi) {
+            const unsigned long long ts = hipmr_ld_agent(dtstart + (cand & (HIPMR_RING - 1)));
+            pred = ts <= G || ts >= fresh;
+          }
+          const unsigned long long m = __ballot(pred);
+          const int kk = m ? 63 - __builtin_clzll(m) : 0;
+          lo = lo + (unsigned long long)kk * step;
+          hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+        }
+        hint = lo;
+        const unsigned long long slot = lo & (HIPMR_RING - 1);
+        const hipmr_sjob J = dring[slot];
+        const unsigned long long js = hipmr_ld_agent(dtstart + slot);
+        const int k = (int)(G - js);
+        const float2 r = hipmr_job_dispatch(J, k, lane);
+        const bool mx = J.tmpl == 3;
+        const int ntiles = hipmr_job_ntiles(J), ng = (ntiles + 63) / 64, g = k / 64;
+        const int gsize = ntiles - 64 * g < 64 ? ntiles - 64 * g : 64;
+        unsigned int old = 0;
+        if (lane == 0) {
+          tpart[G & tp_mask] = r;
+          old = __hip_atomic_fetch_add(gdone + slot * 128 + g, 1u, __ATOMIC_ACQ_REL,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+          if (old + 1 == (unsigned)gsize)                  // ready for the slot's next job
+            __hip_atomic_store(gdone + slot * 128 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        old = __shfl(old, 0, 64);
+        if (old + 1 == (unsigned)gsize) {                 // this wave completed group g
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          const double2 gv = hipmr_fin_group(mx, tpart, js + 64ull * g, tp_mask, 0, gsize, lane);
+          double2 tot;
+          bool last = ng == 1;
+          if (ng == 1) {
+            tot = hipmr_fin_level2(mx, lane == 0, gv, false, gv);
+          } else {
+            unsigned int o2 = 0;
+            if (lane == 0) {
+              gpart[slot * 128 + g] = gv;
+              o2 = __hip_atomic_fetch_add(jdone + slot, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+              if (o2 + 1 == (unsigned)ng)
+                __hip_atomic_store(jdone + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            o2 = __shfl(o2, 0, 64);
+            last = o2 + 1 == (unsigned)ng;
+            if (last) {
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+              tot = hipmr_fin_groups(mx, gpart + slot * 128, ng, lane);
+            }
+          }
+          if (last && lane == 0) {
+            hipmr_job_post(J, tot, hr_flags + slot, lo + 1);
+            __hip_atomic_fetch_add(ctrl + 16, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+      done = avail;
+      __syncthreads();
+    }
+  }
+}
 )HIP";
 
 int64_t now_ns() {
@@ -419,7 +680,7 @@ int job_tiles(const hipmr_sjob& j, int head) {
     const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
     const long long body = j.n - ab;
     long long p = 1;
-    while (head >= 0 && p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
+    while (p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
     const long long t = (body + tt0 * p - 1) / (tt0 * p);
     return (int)std::max<long long>(t, 1);
 }
@@ -432,6 +693,36 @@ uint64_t job_bytes(const hipmr_sjob& j) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Device workspace of the resident mode: control words, the device copy of
+// the descriptor ring and the first tile of each, per slot 128 group counters
+// and group values, per slot a job counter, and the ring of tile partials.
+struct ResLayout {
+    size_t ctrl, dring, dtstart, gdone, jdone, gpart, tpart, total;
+    uint64_t tp;          // tile partials (a power of two >= max_batch_tiles)
+};
+
+ResLayout res_layout(const hipmr_server_config& c) {
+    ResLayout L{};
+    uint64_t tp = 8192;
+    while (tp < (uint64_t)c.max_batch_tiles) tp <<= 1;
+    L.tp = tp;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + 255) & ~size_t(255);
+        return at;
+    };
+    L.ctrl = take(kCtrlBytes);
+    L.dring = take((size_t)kRing * sizeof(DevJob));
+    L.dtstart = take((size_t)kRing * 8);
+    L.gdone = take((size_t)kRing * 128 * 4);
+    L.jdone = take((size_t)kRing * 4);
+    L.gpart = take((size_t)kRing * 128 * 16);
+    L.tpart = take((size_t)tp * 8);
+    L.total = off;
+    return L;
+}
+
 size_t slot_bytes(const hipmr_server_config& c) {
     return align256((size_t)c.max_batch_jobs * sizeof(DevJob)) + align256((size_t)c.max_batch_tiles * 8);
 }
@@ -443,10 +734,11 @@ hipmr_server_config resolved(const hipmr_server_config* in) {
     if (c.nstreams == 0) c.nstreams = 4;
     if (c.max_batch_jobs == 0) c.max_batch_jobs = 1024;
     if (c.max_batch_tiles == 0) c.max_batch_tiles = 1 << 18;
-    if (c.blocks_per_cu == 0) c.blocks_per_cu = 8;
     if (c.max_batch_bytes == 0) c.max_batch_bytes = 16ull << 20;
     if (c.solo_bytes == 0) c.solo_bytes = std::min<uint64_t>(4ull << 20, c.max_batch_bytes);
     if (c.batch_backlog == 0) c.batch_backlog = 8;
+    if (c.resident && c.blocks_per_cu == 0) c.blocks_per_cu = 1;
+    if (c.blocks_per_cu == 0) c.blocks_per_cu = 8;
     return c;
 }
 
@@ -467,6 +759,7 @@ std::string serve_source(const std::string& prefix) {
     rep("@@PREFIX@@", prefix);
     rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
     rep("@@NINLINE@@", std::to_string(kInlineJobs));
+    rep("@@RING@@", std::to_string(kRing));
     return src;
 }
 
@@ -478,9 +771,10 @@ struct hipmr_server {
     std::shared_ptr<CodeObject> co;
     hipModule_t module = nullptr;
     hipFunction_t f_s1 = nullptr, f_s2 = nullptr, f_one1 = nullptr, f_one2 = nullptr;
-    hipFunction_t f_i1 = nullptr, f_i2 = nullptr, f_one = nullptr;
+    hipFunction_t f_i1 = nullptr, f_i2 = nullptr, f_one = nullptr, f_res = nullptr;
     std::string prefix;
     int cus = 256;
+
 
     struct Pending {
         hipmr_sjob job;
@@ -490,6 +784,30 @@ struct hipmr_server {
         int tiles;
         int head;
     };
+    // resident mode: the host ring (mapped host memory), the device workspace
+    // parts, and the state of the instance on the device
+    struct Res {
+        hipStream_t stream = nullptr;
+        uint64_t* hdr = nullptr;            // host view; [0] published, [16] stop word, [32] exit word
+        DevJob* jobs = nullptr;
+        uint64_t* tstart = nullptr;
+        uint64_t* flags = nullptr;
+        void *hdr_d = nullptr, *jobs_d = nullptr, *tstart_d = nullptr, *flags_d = nullptr;
+        char* ws = nullptr;
+        ResLayout L{};
+        int grid = 0;
+        uint64_t deadline_ticks = 0;
+        uint64_t next_seq = 0, next_tile = 0, epoch = 0;
+        bool running = false;
+        int64_t launched_ns = 0, last_busy_ns = 0, last_query_ns = 0;
+        struct Flight {
+            Pending p;
+            uint64_t seq, tile0, tiles;
+            int64_t published_ns;
+            int32_t on_device;
+        };
+        std::deque<Flight> flights;         // published, not completed, in publish order
+    } res;
     struct Slot {
         hipStream_t stream = nullptr;
         DevJob* host_desc = nullptr;    // pinned host memory
@@ -528,6 +846,14 @@ struct hipmr_server {
     // Frees what hipmr_server_create allocated, also when it failed part
     // way; runs after the loop's thread has ended (or was never started).
     ~hipmr_server() {
+        if (res.stream) {
+            // the instance reads the host ring until it exits: stop it (if the
+            // loop did not) and wait before the ring is freed
+            if (res.running && res.hdr) stop_instance();
+            (void)hipStreamSynchronize(res.stream);
+            (void)hipStreamDestroy(res.stream);
+        }
+        if (res.hdr) (void)hipHostFree(res.hdr);
         for (auto& sl : slots) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
@@ -624,27 +950,166 @@ struct hipmr_server {
         return HIPMR_OK;
     }
 
-    // One pass of the loop; returns true if it did anything.
-    bool step() {
-        bool progressed = false;
+    // ------------------------------------------------------------ resident
+    // Stops the running instance at the next job index: it finishes the jobs
+    // it accepted and exits.
+    void stop_instance() {
+        __atomic_store_n(&res.hdr[16], (res.epoch << kEpochShift) | res.next_seq, __ATOMIC_RELEASE);
+        res.running = false;
+    }
+
+    // Launches an instance that takes the jobs from res.next_seq on; it runs
+    // after the previous instance (same stream) has exited.
+    hipmr_status launch_instance() {
+        ++res.epoch;
+        char* w = res.ws;
+        void* ctrl = w + res.L.ctrl;
+        hipError_t e = hipMemsetAsync(ctrl, 0, kCtrlBytes, res.stream);
+        void* dring = w + res.L.dring;
+        void* dtstart = w + res.L.dtstart;
+        void* gdone = w + res.L.gdone;
+        void* jdone = w + res.L.jdone;
+        void* gpart = w + res.L.gpart;
+        void* tpart = w + res.L.tpart;
+        unsigned long long mask = res.L.tp - 1, jb = res.next_seq, tb = res.next_tile, ep = res.epoch,
+                           dl = res.deadline_ticks;
+        void* a[17] = {&res.hdr_d, &res.jobs_d, &res.tstart_d, &res.flags_d, &ctrl, &dring, &dtstart,
+                       &gdone, &jdone, &gpart, &tpart, &mask, &jb, &tb, &ep, &dl};
+        if (e == hipSuccess)
+            e = hipModuleLaunchKernel(f_res, (unsigned)res.grid, 1, 1, 1024, 1, 1, 0, res.stream, a, nullptr);
+        if (e != hipSuccess)
+            return fail(HIPMR_E_HIP, std::string("resident launch: ") + hipGetErrorString(e));
+        res.running = true;
+        res.launched_ns = now_ns();
+        return HIPMR_OK;
+    }
+
+    void fail_flights(hipmr_status st) {
         const int64_t t = now_ns();
-        {   // arrivals
-            std::lock_guard<std::mutex> lk(mu);
-            while (!incoming.empty()) {
-                waiting.push_back(incoming.front());
-                incoming.pop_front();
+        for (const auto& f : res.flights) {
+            admitted -= f.p.bytes;
+            complete(f.p, st, f.on_device, f.published_ns, t);
+        }
+        res.flights.clear();
+    }
+
+    bool step_resident() {
+        bool progressed = take_arrivals();
+        const int64_t t = now_ns();
+        // completions: each job's flag holds its index + 1 once its result is written
+        for (auto it = res.flights.begin(); it != res.flights.end();) {
+            if (*(volatile uint64_t*)&res.flags[it->seq & (kRing - 1)] == it->seq + 1) {
+                admitted -= it->p.bytes;
+                complete(it->p, HIPMR_OK, it->on_device, it->published_ns, now_ns());
+                it = res.flights.erase(it);
                 progressed = true;
+            } else {
+                ++it;
             }
-            while (sched && sched_next < sched_n && sched_t0 + sched[sched_next].arrival_ns <= t) {
-                const hipmr_sjob& j = sched[sched_next];
-                Pending p{j, (1ull << 62) + (uint64_t)sched_next, sched_t0 + j.arrival_ns, job_bytes(j), 0,
-                          job_head(j)};
-                p.tiles = job_tiles(j, p.head);
-                waiting.push_back(p);
-                ++sched_next;
+        }
+        // watchdog: errors of the stream, and jobs the instance can no longer finish
+        if (!res.flights.empty() && t - res.flights.front().published_ns > kWatchdogNs &&
+            t - res.last_query_ns > kWatchdogNs) {
+            res.last_query_ns = t;
+            hipError_t q = hipStreamQuery(res.stream);
+            const bool late = t - res.flights.front().published_ns > (int64_t)(2.5 * kLifeS * 1e9);
+            if ((q != hipSuccess && q != hipErrorNotReady) || late) {
+                std::lock_guard<std::mutex> lk(mu);
+                worker_status = HIPMR_E_HIP;
+                worker_error = q != hipSuccess && q != hipErrorNotReady
+                                   ? std::string("resident kernel: ") + hipGetErrorString(q)
+                                   : "resident kernel: jobs not completed by the instance's deadline";
+            }
+            if ((q != hipSuccess && q != hipErrorNotReady) || late) {
+                fail_flights(HIPMR_E_HIP);
+                if (res.running) stop_instance();
                 progressed = true;
             }
         }
+        // admission: in arrival order while the budget, the descriptor ring and
+        // the ring of tile partials have room
+        while (!waiting.empty()) {
+            const Pending& p = waiting.front();
+            const uint64_t tiles = (uint64_t)std::max(1, p.tiles);
+            const uint64_t oldest_seq = res.flights.empty() ? res.next_seq : res.flights.front().seq;
+            const uint64_t oldest_tile = res.flights.empty() ? res.next_tile : res.flights.front().tile0;
+            if (admitted + p.bytes > cfg.hbm_budget_bytes) break;
+            if (res.next_seq - oldest_seq >= (uint64_t)kRing) break;
+            if (res.next_tile + tiles - oldest_tile > res.L.tp) break;
+            if (!res.running) {
+                hipmr_status st = launch_instance();
+                if (st != HIPMR_OK) {
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        worker_status = st;
+                        worker_error = last_error();
+                    }
+                    complete(p, st, 0, t, now_ns());
+                    waiting.pop_front();
+                    progressed = true;
+                    continue;
+                }
+            }
+            const uint64_t slot = res.next_seq & (kRing - 1);
+            res.jobs[slot] = DevJob{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
+                                    p.job.out, p.job.a, p.job.b};
+            res.tstart[slot] = res.next_tile;
+            __atomic_store_n(&res.hdr[0], res.next_seq + 1, __ATOMIC_RELEASE);
+            res.flights.push_back({p, res.next_seq, res.next_tile, tiles, now_ns(),
+                                   (int32_t)res.flights.size() + 1});
+            admitted += p.bytes;
+            ++res.next_seq;
+            res.next_tile += tiles;
+            waiting.pop_front();
+            progressed = true;
+        }
+        // the instance: a new one every kRotateNs (so none reaches its
+        // deadline), none while idle for kIdleStopNs
+        const int64_t t2 = now_ns();
+        if (!res.flights.empty() || !waiting.empty()) res.last_busy_ns = t2;
+        if (res.running) {
+            if (t2 - res.last_busy_ns > kIdleStopNs) {
+                stop_instance();
+            } else if (t2 - res.launched_ns > kRotateNs) {
+                stop_instance();
+                hipmr_status st = launch_instance();
+                if (st != HIPMR_OK) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    worker_status = st;
+                    worker_error = last_error();
+                }
+            }
+        }
+        return progressed;
+    }
+
+    // Arrivals: submitted jobs and scheduled jobs whose time has come join
+    // the waiting queue.
+    bool take_arrivals() {
+        bool progressed = false;
+        const int64_t t = now_ns();
+        std::lock_guard<std::mutex> lk(mu);
+        while (!incoming.empty()) {
+            waiting.push_back(incoming.front());
+            incoming.pop_front();
+            progressed = true;
+        }
+        while (sched && sched_next < sched_n && sched_t0 + sched[sched_next].arrival_ns <= t) {
+            const hipmr_sjob& j = sched[sched_next];
+            Pending p{j, (1ull << 62) + (uint64_t)sched_next, sched_t0 + j.arrival_ns, job_bytes(j), 0,
+                      job_head(j)};
+            p.tiles = job_tiles(j, p.head);
+            waiting.push_back(p);
+            ++sched_next;
+            progressed = true;
+        }
+        return progressed;
+    }
+
+    // One pass of the loop; returns true if it did anything.
+    bool step() {
+        if (cfg.resident) return step_resident();
+        bool progressed = take_arrivals();
         // completions
         for (Slot& s : slots) {
             if (!s.busy) continue;
@@ -783,13 +1248,13 @@ struct hipmr_server {
         while (true) {
             bool progressed = step();
             if (stop.load()) {
-                bool busy = false;
+                bool busy = !res.flights.empty();
                 for (Slot& s : slots) busy |= s.busy;
                 std::lock_guard<std::mutex> lk(mu);
                 if (!busy && incoming.empty() && waiting.empty()) break;
             }
             if (!progressed) {
-                bool busy = false;
+                bool busy = !res.flights.empty();
                 for (Slot& s : slots) busy |= s.busy;
                 std::unique_lock<std::mutex> lk(mu);
                 bool sched_pending = sched && sched_next < sched_n;
@@ -801,6 +1266,7 @@ struct hipmr_server {
                 }
             }
         }
+        if (res.running) stop_instance();
     }
 };
 
@@ -817,6 +1283,9 @@ hipmr_status validate_job(const hipmr_server* s, const hipmr_sjob* j) {
         return fail(HIPMR_E_INVALID, "an input array of the job's template is NULL");
     if (job_bytes(*j) > s->cfg.hbm_budget_bytes)
         return fail(HIPMR_E_BUDGET, "the job alone exceeds the memory budget");
+    if (job_tiles(*j, job_head(*j)) > kMaxJobTiles)
+        return fail(HIPMR_E_UNSUPPORTED, "the job has more than 8192 tiles (over 2^26 float32 or "
+                                         "2^27 bfloat16 elements)");
     if (job_tiles(*j, job_head(*j)) > s->cfg.max_batch_tiles)
         return fail(HIPMR_E_BUDGET, "the job has more tiles than max_batch_tiles");
     return HIPMR_OK;
@@ -830,6 +1299,7 @@ int64_t hipmr_server_now_ns(void) { return now_ns(); }
 
 size_t hipmr_server_workspace_bytes(const hipmr_server_config* in) {
     hipmr_server_config c = resolved(in);
+    if (c.resident) return res_layout(c).total;
     return (size_t)c.nstreams * slot_bytes(c);
 }
 
@@ -862,10 +1332,50 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
     if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
     struct { hipFunction_t* f; const char* suffix; } fns[] = {
         {&s->f_s1, "_s1"}, {&s->f_s2, "_s2"}, {&s->f_one1, "_one1"}, {&s->f_one2, "_one2"},
-        {&s->f_i1, "_i1"}, {&s->f_i2, "_i2"}, {&s->f_one, "_one"}};
+        {&s->f_i1, "_i1"}, {&s->f_i2, "_i2"}, {&s->f_one, "_one"}, {&s->f_res, "_res"}};
     for (auto& f : fns) {
         e = hipModuleGetFunction(f.f, s->module, (s->prefix + f.suffix).c_str());
         if (e != hipSuccess) return fail(HIPMR_E_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+    }
+    if (c.resident) {
+        auto& r = s->res;
+        r.L = res_layout(c);
+        r.ws = (char*)workspace;
+        int per_cu = 0, khz = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, s->f_res, 1024, 0) != hipSuccess ||
+            per_cu < 1)
+            return fail(HIPMR_E_HIP, "the resident kernel does not fit a CU with 1024 threads");
+        r.grid = std::min(c.blocks_per_cu, per_cu) * s->cus;
+        if (r.grid < 2) return fail(HIPMR_E_HIP, "the resident kernel needs at least two blocks");
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
+            khz < 1000 || khz > 10000000)
+            return fail(HIPMR_E_HIP, "the device wall clock rate is unknown");
+        r.deadline_ticks = (uint64_t)(kLifeS * 1e3 * khz);
+        const size_t ring = 512 + (size_t)kRing * (sizeof(DevJob) + 16);
+        // default-priority, non-blocking stream; the ring in mapped, coherent host memory
+        if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipHostMalloc((void**)&r.hdr, ring, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+            return fail(HIPMR_E_HIP, "creating the resident stream or its host ring failed");
+        std::memset(r.hdr, 0, ring);
+        r.jobs = (DevJob*)((char*)r.hdr + 512);
+        r.tstart = (uint64_t*)(r.jobs + kRing);
+        r.flags = r.tstart + kRing;
+        void* hd = nullptr;
+        if (hipHostGetDevicePointer(&hd, r.hdr, 0) != hipSuccess)
+            return fail(HIPMR_E_HIP, "hipHostGetDevicePointer failed for the host ring");
+        r.hdr_d = hd;
+        r.jobs_d = (char*)hd + 512;
+        r.tstart_d = (char*)r.jobs_d + (size_t)kRing * sizeof(DevJob);
+        r.flags_d = (char*)r.tstart_d + (size_t)kRing * 8;
+        // no instance yet: the stop word names epoch 0, which never runs
+        r.hdr[16] = 0;
+        if (hipMemsetAsync(workspace, 0, r.L.total, r.stream) != hipSuccess ||
+            hipStreamSynchronize(r.stream) != hipSuccess)
+            return fail(HIPMR_E_HIP, "clearing the resident workspace failed");
+        hipmr_server* raw = s.get();
+        s->worker = std::thread([raw] { raw->loop(); });
+        *out = s.release();
+        return HIPMR_OK;
     }
     s->slots.resize(c.nstreams);
     char* base = (char*)workspace;

@@ -273,7 +273,7 @@ class Kernel:
         self._h = h
         (self.is_reduce, self.result_dtype, self.vectorizable, self.vec, self.args,
          self._sized, _) = meta
-        self._tls = threading.local()     # per-thread argument buffers (see marshal)
+        self._tls = None                  # per-thread argument buffers, made by the first marshal
 
     @staticmethod
     def _metadata(h, dtypes):
@@ -328,12 +328,18 @@ class Kernel:
         pair of buffers per handle, rewritten by its next call."""
         if len(args) != len(self.args):
             raise InvalidError(f"expected {len(self.args)} arguments, got {len(args)}")
-        bufs = getattr(self._tls, "bufs", None)
+        tls = self._tls
+        if tls is None:
+            with _META_LOCK:
+                if self._tls is None:
+                    self._tls = threading.local()
+            tls = self._tls
+        bufs = getattr(tls, "bufs", None)
         if bufs is None:
             nargs = max(1, len(args))
             store = (ctypes.c_uint64 * nargs)()
             base = ctypes.addressof(store)
-            bufs = self._tls.bufs = (store, (ctypes.c_void_p * nargs)(*range(base, base + 8 * nargs, 8)))
+            bufs = tls.bufs = (store, (ctypes.c_void_p * nargs)(*range(base, base + 8 * nargs, 8)))
         store, ptrs = bufs
         for k, (decl, val) in enumerate(zip(self.args, args)):
             if decl.pointer:
@@ -377,6 +383,8 @@ def _check_out(out, dtype_code, count, what):
     import torch
     if not isinstance(out, torch.Tensor):
         raise InvalidError(f"{what}: out must be a device tensor")
+    if not dtype_code:
+        raise MismatchError(f"{what}: the handle is an elementwise handle (it has no result type)")
     want = torch_dtype(dtype_code)
     if out.dtype != want:
         raise MismatchError(f"{what}: out has dtype {out.dtype}, the result type is {want}")
@@ -730,7 +738,7 @@ class ServerConfig(ctypes.Structure):
                 ("max_batch_jobs", ctypes.c_int32), ("max_batch_tiles", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("max_batch_bytes", ctypes.c_uint64),
                 ("solo_bytes", ctypes.c_uint64), ("batch_backlog", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("resident", ctypes.c_int32)]
 
 
 def _sjob_dtype():
@@ -755,12 +763,14 @@ class Server:
     ``Server.JOB`` (device pointers as integers)."""
 
     def __init__(self, hbm_budget_bytes=0, nstreams=0, max_batch_jobs=0, max_batch_tiles=0,
-                 blocks_per_cu=0, max_batch_bytes=0, solo_bytes=0, batch_backlog=0, device=None):
+                 blocks_per_cu=0, max_batch_bytes=0, solo_bytes=0, batch_backlog=0, resident=0,
+                 device=None):
         import torch
         self.JOB = _sjob_dtype()
         self.COMPLETION = _completion_dtype()
         self.cfg = ServerConfig(hbm_budget_bytes, nstreams, max_batch_jobs, max_batch_tiles,
-                                blocks_per_cu, max_batch_bytes, solo_bytes, batch_backlog, 0)
+                                blocks_per_cu, max_batch_bytes, solo_bytes, batch_backlog,
+                                int(resident))
         nbytes = lib().hipmr_server_workspace_bytes(ctypes.byref(self.cfg))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8,
                                      device=device or torch.device("cuda"))

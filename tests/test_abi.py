@@ -357,3 +357,31 @@ def test_workspace_sizes_follow_their_documented_rules():
     seg = [hm.segmented_workspace_bytes(red, 4096, n) for n in (0, 1 << 20, 1 << 28)]
     assert seg == sorted(seg) and seg[0] > 0
     assert hm.segmented_workspace_bytes(red, 8192, 1 << 20) > hm.segmented_workspace_bytes(red, 4096, 1 << 20)
+
+
+def test_binding_checks_outputs_and_offsets_before_the_library():
+    """The C ABI takes bare pointers, so the binding checks what the library
+    will write: the output tensor's dtype (the result type; none for an
+    elementwise handle), contiguity and length, and the segmented offsets
+    (int64, nseg + 1 values).  All of it is refused before any device work."""
+    import torch
+    r = hm.compile("x[i]", "float: const float *x", name="outchk")
+    e = hm.compile("z[i] = x[i]", "float *z, const float *x", name="outchk_ew")
+    x = torch.zeros(8)
+    with pytest.raises(hm.MismatchError, match="elementwise handle"):
+        hm.scan(e, "a+b", "0", 4, [x, x], torch.empty(4))
+    with pytest.raises(hm.MismatchError, match="result type"):
+        hm.scan(r, "a+b", "0", 4, [x], torch.empty(4, dtype=torch.float64))
+    with pytest.raises(hm.InvalidError, match="4 are written"):
+        hm.scan(r, "a+b", "0", 4, [x], torch.empty(3))
+    with pytest.raises(hm.InvalidError, match="contiguous"):
+        hm.scan(r, "a+b", "0", 4, [x], torch.empty(8)[::2])
+    with pytest.raises(hm.MismatchError, match="result type"):
+        hm.reduce(r, None, "a+b", "0", 4, [x], torch.empty((), dtype=torch.int32))
+    offs = torch.tensor([0, 4, 8])
+    with pytest.raises(hm.InvalidError, match="2 are written"):
+        hm.reduce_segmented(r, "a+b", "0", offs, 8, [x], torch.empty(1))
+    with pytest.raises(hm.MismatchError, match="int64"):
+        hm.reduce_segmented(r, "a+b", "0", offs.to(torch.int32), 8, [x], torch.empty(2))
+    with pytest.raises(hm.InvalidError, match="nseg"):
+        hm.reduce_segmented(r, "a+b", "0", offs.reshape(1, 3), 8, [x], torch.empty(2))

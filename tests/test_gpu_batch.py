@@ -50,7 +50,7 @@ def check_segments(op, got, offsets, x, y, what, stride=1):
     for s in range(0, len(offsets) - 1, stride):
         a, b = int(offsets[s]), int(offsets[s + 1])
         r = oracle.reduce(sig, mp, comb, neu, b - a, [x[a:b], y[a:b]])
-        assert_reduce(float(g[s]), r, f"{what} segment {s} [{a}, {b})")
+        assert_reduce(float(g[s]), r, f"{what} segment {s} [{a}, {b})", bare=True)
 
 
 @pytest.mark.parametrize("op", ["sum", "max", "dot"])
@@ -176,6 +176,52 @@ def test_graph_capture_and_replay(dev, seg_data, handles):
             assert g[s] == np.max(x[a:b]), s
         od.copy_(torch.from_numpy(offsets))
         torch.cuda.synchronize()
+
+
+def test_concurrent_graph_fork_join(dev, seg_data, handles):
+    """The three ops on three streams inside one captured graph (fork / join
+    with events), as the benchmark replays them: every replay equals the
+    eager results, with eager work and synchronisations in between."""
+    offsets, x, y, od, xd, yd = seg_data
+    stream = torch.cuda.Stream()
+    side = {"max": torch.cuda.Stream(), "dot": torch.cuda.Stream()}
+    outs = {op: torch.empty(len(offsets) - 1, dtype=torch.float32, device=dev) for op in OPS}
+    ws = {op: torch.empty(hm.segmented_workspace_bytes(handles[op], len(offsets) - 1, x.size),
+                          dtype=torch.uint8, device=dev) for op in OPS}
+
+    def one(op, st):
+        hm.reduce_segmented(handles[op], OPS[op][2], OPS[op][3], od, x.size, [xd, yd], outs[op],
+                            workspace_buf=ws[op], stream=st)
+
+    with torch.cuda.stream(stream):
+        def issue():
+            fork = torch.cuda.Event()
+            fork.record(stream)
+            for op, st in side.items():
+                st.wait_event(fork)
+                one(op, st)
+            one("sum", stream)
+            for st in side.values():
+                join = torch.cuda.Event()
+                join.record(st)
+                stream.wait_event(join)
+        for op in OPS:
+            one(op, stream)                       # warm-up loads the code objects
+        torch.cuda.synchronize()
+        eager = {op: outs[op].clone() for op in OPS}
+        graph = hm.Graph()
+        with graph.capture(stream):
+            issue()
+        for rep in range(4):
+            for op in OPS:
+                outs[op].fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.launch(stream)
+            stream.synchronize()
+            for op in OPS:
+                assert torch.equal(outs[op], eager[op]), (rep, op)
+            _ = (xd * 2).sum().item()             # unrelated eager work between replays
+    torch.cuda.synchronize()
 
 
 def test_graph_capture_requires_warm_kernels(dev):

@@ -33,7 +33,7 @@ def dev():
 @pytest.fixture(scope="module")
 def data():
     rng = np.random.default_rng(21)
-    nmax = max(SWEEP_N) + 8
+    nmax = max(SWEEP_N + LARGE_N) + 8
     x = rng.uniform(-1, 1, nmax).astype(np.float32)
     y = rng.uniform(-1, 1, nmax).astype(np.float32)
     return x, y

@@ -23,7 +23,10 @@ def dev():
 
 
 def run_scan(k, combine, neutral, n, args, out_dtype, dev, exclusive=False, out_offset=0, config=None):
-    buf = torch.full((n + out_offset + 1,), 7, dtype=out_dtype, device=dev)
+    if out_dtype == torch.uint32:      # filled as int32 (same bits), seen as uint32
+        buf = torch.full((n + out_offset + 1,), 7, dtype=torch.int32, device=dev).view(torch.uint32)
+    else:
+        buf = torch.full((n + out_offset + 1,), 7, dtype=out_dtype, device=dev)
     out = buf[out_offset:out_offset + n]
     hm.scan(k, combine, neutral, n, args, out, exclusive=exclusive, config=config)
     torch.cuda.synchronize()
@@ -149,11 +152,11 @@ def test_scalar_map_and_generic_combine(dev):
     kd = dev_array(k.view(np.int32))
     sig = "unsigned: const unsigned *k"
     h = hm.compile("k[n - 1 - i]", sig, name="scan_rev")          # not name[i]: one-element path
-    g = host_bits(run_scan(h, "a+b", "0u", n, [kd], torch.int32, dev)).view(np.uint32)
+    g = host_bits(run_scan(h, "a+b", "0u", n, [kd], torch.uint32, dev))
     r = oracle.scan(sig, "k[n - 1 - i]", "a+b", "0u", n, [k])
     assert np.array_equal(g.astype(np.int64), r.values)
     h2 = hm.compile("k[i]", sig, name="scan_or")
-    g = host_bits(run_scan(h2, "a|b", "0u", n, [kd], torch.int32, dev)).view(np.uint32)
+    g = host_bits(run_scan(h2, "a|b", "0u", n, [kd], torch.uint32, dev))
     r = oracle.scan(sig, "k[i]", "a|b", "0u", n, [k])
     assert r.op == "generic" and np.array_equal(g.astype(np.int64), r.values)
 
@@ -188,10 +191,11 @@ def test_empty_and_errors(dev):
                 workspace_buf=torch.empty(16, dtype=torch.uint8, device=dev))
 
 
-def test_scan_at_scale_sampled(dev):
+def test_scan_at_scale_every_prefix(dev):
     """n = 2^28 int32 -> int64 inclusive sum (the plain workload's k, 3 GB of
-    traffic): prefixes at sampled positions against the oracle's reduce of
-    that prefix, and the last against the whole reduce."""
+    traffic): every prefix against the oracle's scan, taken in chunks of 2^24
+    elements, each chunk scanned from the previous chunk's last prefix as its
+    initial value (so every entry is the exact prefix over [0, i])."""
     import workloads
     n = 1 << 28
     k = workloads.plain_k(n)
@@ -200,15 +204,16 @@ def test_scan_at_scale_sampled(dev):
     out = torch.empty(n, dtype=torch.int64, device=dev)
     hm.scan(h, "a+b", "0", n, [kd], out)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(91)
-    picks = sorted(set(rng.integers(0, n, 6).tolist()) | {0, n // 2 + 3, n - 1})
-    got = out[torch.tensor(picks, device=dev)].cpu().numpy()
-    total, prev = 0, 0
-    for p, g in zip(picks, got.tolist()):
-        # the prefix [0, p] as the oracle's reduce of consecutive pieces
-        total += oracle.reduce("long: const int *k", "k[i]", "a+b", "0", p + 1 - prev,
-                               [k[prev:p + 1]]).value
-        prev = p + 1
-        assert g == total, p
-    del out
+    got = out.cpu().numpy()
+    del out, kd
     torch.cuda.empty_cache()
+    step = 1 << 24
+    carry = 0
+    for a in range(0, n, step):
+        b = min(a + step, n)
+        r = oracle.scan("long: const int *k", "k[i]", "a+b", str(carry), b - a, [k[a:b]])
+        assert r.exact
+        bad = np.nonzero(got[a:b] != r.values)[0]
+        assert bad.size == 0, f"{bad.size} prefixes differ in [{a}, {b}), first at {a + bad[0]}"
+        carry = int(r.values[-1])
+    assert carry == int(np.sum(k, dtype=np.int64))
