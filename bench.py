@@ -46,6 +46,9 @@ def parse():
     p.add_argument("--extensions", default="compile,dot,precision,batched,served,scan,shifted,cg,lazy,complex",
                    help="comma list of the extension measurements to run "
                         "(compile, dot, precision, batched, served, scan, shifted, cg, lazy, complex)")
+    p.add_argument("--batched-eager-only", action="store_true",
+                   help="batched leg: the tuned ops eagerly only (no graphs, no per-segment "
+                        "baseline), for counter runs")
     p.add_argument("--serving-rates", default="",
                    help="comma list of jobs/s (default: 2000,10000,50000 and the 200000 stress rate)")
     p.add_argument("--serving-duration", type=float, default=4.0,
@@ -457,9 +460,11 @@ def bench_compile(torch, hm, workloads, dev, stream, reps=5, launches=2000, hits
                         binding.prepare_reduce(k, *combine)
                     return k
 
+                held = None
                 for phase in ("cold", "disk", "memory"):
                     if phase == "disk":
                         binding.cache_drop_memory()
+                    held = None                 # no handle for the text is held: not a handle hit
                     t0 = time.perf_counter()
                     held = build()
                     times[phase].append((time.perf_counter() - t0) * 1e3)
@@ -792,7 +797,8 @@ def bench_complex(torch, hm, workloads, dev, stream, reps=10):
     return res
 
 
-def bench_batched(torch, hm, workloads, dev, checks, reps=12, baseline_reps=2, copies=3):
+def bench_batched(torch, hm, workloads, dev, checks, reps=12, baseline_reps=2, copies=3,
+                  eager_only=False):
     """4096 lognormal segments (62,032,791 float32): segmented sum, max and dot
     (three persistent launch sequences) replayed from HIP graphs, against one
     plain launch pair per segment (eager, and captured in a graph).  The
@@ -848,6 +854,12 @@ def bench_batched(torch, hm, workloads, dev, checks, reps=12, baseline_reps=2, c
                 join.record(st)
                 stream.wait_event(join)
         issue_serial()
+        if eager_only:
+            for c in range(copies):
+                issue_serial(c)
+            torch.cuda.synchronize()
+            return {"eager_only": True, "symbols": {op: ks[op].last_symbols() for op in ops},
+                    "tuned": tuned}
         issue_concurrent()
         torch.cuda.synchronize()
         graphs = {"concurrent": [], "serial": []}
@@ -1176,7 +1188,8 @@ def main():
         line["precision"] = bench_precision(torch, hm, workloads, dev, stream, checks)
         print("precision done", file=sys.stderr, flush=True)
     if "batched" in ext:
-        line["batched"] = bench_batched(torch, hm, workloads, dev, checks)
+        line["batched"] = bench_batched(torch, hm, workloads, dev, checks,
+                                        eager_only=args.batched_eager_only)
         print("batched done", file=sys.stderr, flush=True)
     if "shifted" in ext:
         line["shifted"] = bench_shifted(torch, hm, dev, stream)

@@ -170,8 +170,9 @@ hipmr_status hipmr_elementwise_ex(hipmr_handle h, int64_t n, void *const *args,
                                   const hipmr_launch_config *cfg, void *stream);
 
 /* Bytes of device workspace hipmr_reduce, hipmr_reduce_compensated and
- * hipmr_norm2 need (64 KiB of block partials plus 256 bytes for the norm's
- * scale; independent of n).  Returns 0 for an elementwise or invalid handle. */
+ * hipmr_norm2 need (64 KiB of block partials, 32 KiB of the norm's first-pass
+ * partials and 256 bytes for its scale; independent of n).  Returns 0 for an
+ * elementwise or invalid handle. */
 size_t hipmr_reduce_workspace_bytes(hipmr_handle h, int64_t n);
 
 /* Map-reduce: *out = neutral (+) map(0) (+) ... (+) map(n-1), (+) being
@@ -248,15 +249,16 @@ hipmr_status hipmr_reduce_compensated(hipmr_handle h, int64_t n, void *const *ar
 
 /* L2 norm of a float map: *out (double) = post_scale * sqrt(sum_i map(i)^2),
  * precision extension as above.
- *   passes == 2 (scaled): pass 1 takes the exact max |map(i)| and derives, on
- *     the device, the power of two s that puts it in [1, 2) (exponent clamped
- *     to [-126, 126]); pass 2 accumulates (map(i) * s)^2 with compensation and
- *     the final FP64 step returns post_scale * sqrt(sum) / s.  Reads the data
- *     twice.
+ *   passes == 2 (scaled): pass 1 takes the exact max |map(i)| per block;
+ *     every block of pass 2 (same grid) first derives from those maxima the
+ *     power of two s that puts the largest in [1, 2) (exponent clamped to
+ *     [-126, 126]), then accumulates (map(i) * s)^2 with compensation; the
+ *     final FP64 step returns post_scale * sqrt(sum) / s.  Reads the data
+ *     twice, in three launches.
  *   passes == 1: no scaling, one read; the squares must stay inside the float
  *     range (true for every half or FP8 load: their squares are below 2^32).
- * The scale is kept in the workspace between the two passes.  Errors: as
- * hipmr_reduce_compensated; E_INVALID for passes other than 1 or 2. */
+ * The first pass's maxima and the scale are kept in the workspace.  Errors:
+ * as hipmr_reduce_compensated; E_INVALID for passes other than 1 or 2. */
 hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void *const *args, double post_scale,
                          int32_t passes, void *out, void *workspace, size_t workspace_bytes,
                          const hipmr_launch_config *cfg, void *stream);

@@ -420,37 +420,31 @@ hipmr_status hipmr_norm2(hipmr_handle h, int64_t n, void* const* args, double po
     LaunchCfg cfg;
     st = resolve_cfg(cfgp, kRedBlock, kRedIpt, h->default_vec, kRedBlocksPerCu, &cfg);
     if (st != HIPMR_OK) return st;
-    void* scale_f = (char*)workspace + kScaleOffset;
+    void* amax = (char*)workspace + kAmaxOffset;
     void* scale_d = (char*)workspace + kScaleOffset + 8;
     std::string syms;
-    if (passes == 2) {
-        // pass 1: exact max |map| -> power-of-two scale, written on the device
+    const bool two = passes == 2 && n > 0;     // an empty norm is 0 either way
+    if (two) {
+        // pass 1: exact max |map| per block (the same grid as pass 2)
         KernelSpec a1 = comp_spec(KernelKind::AmaxS1Vector, cfg);
         Stage1 r1;
-        st = stage1_launch(h, a1, true, cfg, n, args, workspace, nullptr, false, stream, &syms, &r1);
-        if (st != HIPMR_OK) return st;
-        KernelSpec a2 = comp_spec(KernelKind::AmaxScale, cfg);
-        a2.block = kStage2Block;
-        a2.ipt = a2.vec = 1;
-        void* fna = nullptr;
-        st = variant_function(h, a2, &fna, &syms);
-        if (st != HIPMR_OK) return st;
-        void* pa[4] = {&workspace, &r1.grid, &scale_f, &scale_d};
-        st = launch(fna, 1, kStage2Block, pa, stream);
+        st = stage1_launch(h, a1, true, cfg, n, args, amax, nullptr, false, stream, &syms, &r1);
         if (st != HIPMR_OK) return st;
     }
-    // pass 2 (or the only pass): compensated sum of (map * scale)^2
+    // pass 2 (or the only pass): compensated sum of (map * scale)^2; with two
+    // passes every block first derives the power-of-two scale from the pass-1
+    // partials (block 0 also stores it for the final fold)
     KernelSpec q1 = comp_spec(KernelKind::CompS1Vector, cfg);
     q1.square = true;
-    q1.scaled = passes == 2;
+    q1.scaled = two;
     Stage1 r2;
-    st = stage1_launch(h, q1, true, cfg, n, args, workspace, scale_f, true, stream, &syms, &r2);
+    st = stage1_launch(h, q1, true, cfg, n, args, workspace, amax, true, stream, &syms, &r2);
     if (st != HIPMR_OK) return st;
     KernelSpec q2 = comp_spec(KernelKind::CompS2, cfg);
     q2.block = kStage2Block;
     q2.ipt = q2.vec = 1;
     q2.norm = true;
-    q2.scaled = passes == 2;
+    q2.scaled = two;
     void* fn2 = nullptr;
     st = variant_function(h, q2, &fn2, &syms);
     if (st != HIPMR_OK) return st;
@@ -826,9 +820,6 @@ hipmr_status hipmr_selftest_compile(int32_t* count) {
                     specs.push_back(q);
                 }
                 specs.push_back(comp_spec(KernelKind::AmaxS1Vector, cfg));
-                KernelSpec sc = comp_spec(KernelKind::AmaxScale, cfg);
-                sc.block = kStage2Block;
-                specs.push_back(sc);
                 for (const KernelSpec& q : specs) {
                     if (!h->prog.info.vectorizable &&
                         (q.kind == KernelKind::CompS1Vector || q.kind == KernelKind::AmaxS1Vector))

@@ -25,6 +25,7 @@
 #include <sstream>
 
 #include "common.h"
+#include "internal.h"
 
 namespace hipmr {
 namespace {
@@ -674,6 +675,38 @@ __device__ __forceinline__ hipmr_dd hipmr_dd_add(hipmr_dd x, hipmr_dd y) {
   return hipmr_two_sum_d(s.hi, s.lo + (x.lo + y.lo));
 }
 
+// The norm's power-of-two scale from its first pass: the max |map| over
+// that pass's block partials (one per block of this grid: both passes use
+// the same geometry), then s = 2^-e, e the exponent of the max clamped to
+// [-126, 126], so the largest scaled magnitude lies in [1, 2).  Every block
+// computes it; block 0 also stores it (float, then double) for the final
+// fold.
+template <int B>
+__device__ __forceinline__ float hipmr_norm_scale(const float* __restrict__ amax,
+                                                  float* __restrict__ store) {
+  __shared__ float hipmr_scale_lds[B / 64];
+  float m = 0.0f;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += B) m = __builtin_elementwise_maximum(m, amax[k]);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = __builtin_elementwise_maximum(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0) hipmr_scale_lds[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = hipmr_scale_lds[0];
+#pragma unroll
+  for (int w = 1; w < B / 64; ++w) m = __builtin_elementwise_maximum(m, hipmr_scale_lds[w]);
+  float s = 1.0f;
+  if (m > 0.0f) {
+    int e = (int)((__float_as_uint(m) >> 23) & 0xffu) - 127;
+    e = e < -126 ? -126 : (e > 126 ? 126 : e);
+    s = __uint_as_float((unsigned int)(127 - e) << 23);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    store[0] = s;
+    *(double*)(store + 2) = (double)s;
+  }
+  return s;
+}
+
 // pairwise sum of one chunk's V terms (fixed tree); the chunk sum then
 // enters the compensated accumulator
 template <int V>
@@ -740,7 +773,9 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   constexpr bool HIPMR_NTL = @@NTL@@, HIPMR_NTS = @@NTS@@;
   constexpr bool HIPMR_SQ = @@SQUARE@@, HIPMR_RUNS = @@RUNS@@, HIPMR_SCALED = @@SCALED@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
-  const float hipmr_sc = HIPMR_SCALED ? *hipmr_scale_p : 1.0f;
+  float hipmr_sc = 1.0f;
+  if constexpr (HIPMR_SCALED)
+    hipmr_sc = hipmr_norm_scale<HIPMR_B>(hipmr_scale_p, (float*)((char*)hipmr_scale_p + @@SCALE_GAP@@));
   float hipmr_s[HIPMR_U], hipmr_e[HIPMR_U];
 #pragma unroll
   for (int u = 0; u < HIPMR_U; ++u) { hipmr_s[u] = 0.0f; hipmr_e[u] = 0.0f; }
@@ -837,7 +872,9 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   typedef @@IDX@@ hipmr_idx;
   constexpr bool HIPMR_SQ = @@SQUARE@@, HIPMR_SCALED = @@SCALED@@;
   const hipmr_idx n = (hipmr_idx)hipmr_n;
-  const float hipmr_sc = HIPMR_SCALED ? *hipmr_scale_p : 1.0f;
+  float hipmr_sc = 1.0f;
+  if constexpr (HIPMR_SCALED)
+    hipmr_sc = hipmr_norm_scale<@@BLOCK@@>(hipmr_scale_p, (float*)((char*)hipmr_scale_p + @@SCALE_GAP@@));
   float hipmr_s = 0.0f, hipmr_cc = 0.0f;
   const long long hipmr_step = (long long)gridDim.x * @@BLOCK@@;
   for (long long hipmr_k = (long long)blockIdx.x * @@BLOCK@@ + threadIdx.x; hipmr_k < hipmr_n;
@@ -879,29 +916,6 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 }
 )HIP";
 
-// Norm pass 1, final step: max |map| over the block partials, then the power
-// of two s = 2^-e (e = exponent of the max, clamped to [-126, 126]) that puts
-// the largest scaled magnitude in [1, 2).
-const char* kAmaxScale = R"HIP(
-extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
-@@KNAME@@(const float* __restrict__ hipmr_partial, int hipmr_g, float* __restrict__ hipmr_scale_f,
-          double* __restrict__ hipmr_scale_d)
-{
-  float m = 0.0f;
-  for (int k = threadIdx.x; k < hipmr_g; k += @@BLOCK@@) m = hipmr_combine(m, hipmr_partial[k]);
-  m = hipmr_block_reduce<@@BLOCK@@>(m, 0.0f);
-  if (threadIdx.x == 0) {
-    float s = 1.0f;
-    if (m > 0.0f) {
-      int e = (int)((__float_as_uint(m) >> 23) & 0xffu) - 127;
-      e = e < -126 ? -126 : (e > 126 ? 126 : e);
-      s = __uint_as_float((unsigned int)(127 - e) << 23);
-    }
-    *hipmr_scale_f = s;
-    *hipmr_scale_d = (double)s;
-  }
-}
-)HIP";
 
 
 // ------------------------------------------------------------ batching
@@ -1448,8 +1462,6 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
             tmpl = kRedS1Vector; tag = "amax"; reduce = true; acc = DT_F32; combine = "max"; break;
         case KernelKind::AmaxS1Scalar:
             tmpl = kRedS1Scalar; tag = "amaxs"; reduce = true; acc = DT_F32; combine = "max"; break;
-        case KernelKind::AmaxScale:
-            tmpl = kAmaxScale; tag = "ascale"; reduce = true; acc = DT_F32; combine = "max"; break;
         case KernelKind::SegPlan: tmpl = kSegPlan; tag = "segplan"; break;
         case KernelKind::SegS1: tmpl = kSegS1; tag = "seg1"; reduce = true; break;
         case KernelKind::SegS2: tmpl = kSegS2; tag = "seg2"; reduce = true; break;
@@ -1556,6 +1568,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
     replace_all(body, "@@RUNS@@", spec.exact_runs ? "true" : "false");
     replace_all(body, "@@NORM@@", spec.norm ? "true" : "false");
     replace_all(body, "@@SCALED@@", spec.scaled ? "true" : "false");
+    replace_all(body, "@@SCALE_GAP@@", std::to_string(kScaleOffset - kAmaxOffset));
     replace_all(body, "@@LDS_SEGS@@", std::to_string(spec.lds_segs));
     replace_all(body, "@@IDX@@", spec.idx64 ? "long long" : "int");
     replace_all(body, "@@BLOCK@@", std::to_string(spec.block));

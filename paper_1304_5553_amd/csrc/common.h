@@ -122,7 +122,7 @@ struct LaunchCfg {
 enum class KernelKind : int32_t {
     EwVector = 0, EwScalar = 1, RedS1Vector = 2, RedS1Scalar = 3, RedS2 = 4,
     CompS1Vector = 5, CompS1Scalar = 6, CompS2 = 7, AmaxS1Vector = 8, AmaxS1Scalar = 9,
-    AmaxScale = 10, SegPlan = 11, SegS1 = 12, SegS2 = 13,
+    SegPlan = 11, SegS1 = 12, SegS2 = 13,
     ScanUpVector = 14, ScanUpScalar = 15, ScanMid = 16, ScanDownVector = 17, ScanDownScalar = 18,
 };
 

@@ -23,9 +23,12 @@ namespace hipmr {
 
 constexpr int kMaxPartials = 8192;           // stage-1 blocks of one reduce
 constexpr int kStage2Block = 256;
-// reduce workspace layout: [0, 64 KiB) block partials; then the norm's scale
-// as a float (+0) and a double (+8)
-constexpr size_t kScaleOffset = (size_t)kMaxPartials * 8;
+// reduce workspace layout: [0, 64 KiB) block partials (FP64 or the
+// reduction's type); [64 KiB, 96 KiB) the norm's first-pass partials (max
+// |map| per block, float), kept apart so the second pass can read them while
+// it writes its own; then the norm's scale as a float (+0) and a double (+8)
+constexpr size_t kAmaxOffset = (size_t)kMaxPartials * 8;
+constexpr size_t kScaleOffset = kAmaxOffset + (size_t)kMaxPartials * 4;
 constexpr size_t kWorkspaceBytes = kScaleOffset + 256;
 
 // Default geometry (overridable per call through hipmr_launch_config), from

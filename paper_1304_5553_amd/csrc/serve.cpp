@@ -444,10 +444,20 @@ extern "C" __global__ void __launch_bounds__(1024)
 // the stop flag and exits.  Blocks 1.. are workers: thread 0 takes 16
 // consecutive tile tickets (one per wave) and polls the block's replica until
 // they are published; each wave reduces its tile with the tile kernels'
-// arithmetic; the wave completing a 64-tile group folds it, and the wave
-// completing the job's last group folds the groups and writes the result
-// (the fold of every other path).  Every wait is bounded: workers exit on the
-// stop flag, and every wave at the instance's deadline.
+// arithmetic; then wave 0 counts the round's tiles into their 64-tile groups
+// (one atomic per group touched), folds each group the round completed, and
+// the wave completing a job's last group folds the groups and writes the
+// result (the fold of every other path).  Every wait is bounded: workers exit
+// on the stop flag, and every wave at the instance's deadline.
+//
+// Memory ordering without cache maintenance: everything one wave hands to
+// another (descriptors, first tiles, tile partials, group values, counters,
+// the published word) is written and read with device-scope atomic accesses,
+// which the L2 keeps coherent across the chip's dies; a writer waits for its
+// data writes to complete (s_waitcnt) before the atomic that publishes them,
+// and a reader issues its data reads only after that atomic's value is
+// known.  (Acquire / release fences at device scope would write back and
+// invalidate the whole L2 at every tile.)
 #define HIPMR_RING @@RING@@
 
 __device__ __forceinline__ unsigned long long hipmr_ld_agent(const unsigned long long* p) {
@@ -458,6 +468,30 @@ __device__ __forceinline__ void hipmr_st_agent(unsigned long long* p, unsigned l
 }
 __device__ __forceinline__ unsigned long long hipmr_ld_sys(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// every memory access issued so far has completed (and the compiler moves no
+// memory access across this point)
+__device__ __forceinline__ void hipmr_drain() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// A job descriptor moved as eight 64-bit words with device-scope accesses.
+__device__ __forceinline__ hipmr_sjob hipmr_job_ld(const hipmr_sjob* p, bool system) {
+  const unsigned long long* w = (const unsigned long long*)p;
+  unsigned long long v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = system ? hipmr_ld_sys(w + k) : hipmr_ld_agent(w + k);
+  hipmr_sjob J;
+  __builtin_memcpy(&J, v, sizeof(J));
+  return J;
+}
+__device__ __forceinline__ void hipmr_job_st(hipmr_sjob* p, const hipmr_sjob& J) {
+  unsigned long long v[8];
+  __builtin_memcpy(v, &J, sizeof(J));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) hipmr_st_agent((unsigned long long*)p + k, v[k]);
 }
 
 __device__ __forceinline__ int hipmr_job_ntiles(const hipmr_sjob& J) {
@@ -490,20 +524,19 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __
                                                                              : ~0ull;
       const unsigned long long lim = P < S ? P : S;
       if (lim > seq) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // system scope: the host's descriptors
         const int cnt = lim - seq < 64 ? (int)(lim - seq) : 64;
         unsigned long long tend = 0;
         if (lane < cnt) {
           const unsigned long long s = seq + lane, slot = s & (HIPMR_RING - 1);
-          const hipmr_sjob J = hr_jobs[slot];
-          const unsigned long long ts = hr_tstart[slot];
-          dring[slot] = J;
+          const hipmr_sjob J = hipmr_job_ld(hr_jobs + slot, true);
+          const unsigned long long ts = hipmr_ld_sys(hr_tstart + slot);
+          hipmr_job_st(dring + slot, J);
           hipmr_st_agent(dtstart + slot, ts);
           tend = ts + (unsigned long long)hipmr_job_ntiles(J);
         }
         tend = __shfl(tend, cnt - 1, 64);
         seq += cnt;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        hipmr_drain();                                   // the ring entries are written
         if (lane < 8)
           hipmr_st_agent(ctrl + 32 + 16 * lane, ((seq - job_base) << 40) | (tend - tile_base));
         continue;
@@ -515,21 +548,34 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __
     }
     const bool drained = closing && hipmr_ld_agent(ctrl + 16) == stop_at - job_base;
     if (drained || wall_clock64() - t0 > deadline || iter > HIPMR_MAX_POLLS) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (lane < 8) hipmr_st_agent(ctrl + 32 + 16 * lane + 2, 1);
       if (lane == 0)
-        __hip_atomic_store(hdr + 32, (epoch << 44) | (seq + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(hdr + 32, (epoch << 44) | (seq + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       return;
     }
     __builtin_amdgcn_s_sleep(1);
   }
 }
 
+// Level 1 of the fold of group g of a job whose first tile is js, read with
+// device-scope loads (the partials of other waves).
+__device__ __forceinline__ double2 hipmr_res_group(bool mx, const unsigned long long* tpart,
+                                                   unsigned long long js, unsigned long long mask,
+                                                   int g, int ntiles, int lane) {
+  const int k = 64 * g + lane;
+  double2 v = hipmr_fin_neutral(mx);
+  if (k < ntiles) {
+    const float2 p = __builtin_bit_cast(float2, hipmr_ld_agent(tpart + ((js + (unsigned long long)k) & mask)));
+    v = make_double2((double)p.x, (double)p.y);
+  }
+  return hipmr_fin_wave(mx, v);
+}
+
 extern "C" __global__ void __launch_bounds__(1024)
 @@PREFIX@@_res(unsigned long long* hdr, const hipmr_sjob* __restrict__ hr_jobs,
                const unsigned long long* __restrict__ hr_tstart, unsigned long long* hr_flags,
                unsigned long long* ctrl, hipmr_sjob* dring, unsigned long long* dtstart,
-               unsigned int* gdone, unsigned int* jdone, double2* gpart, float2* tpart,
+               unsigned int* gdone, unsigned int* jdone, double2* gpart, float2* tpart_f,
                unsigned long long tp_mask, unsigned long long job_base, unsigned long long tile_base,
                unsigned long long epoch, unsigned long long deadline)
 {
@@ -539,11 +585,19 @@ extern "C" __global__ void __launch_bounds__(1024)
                          deadline);
     return;
   }
+  unsigned long long* tpart = (unsigned long long*)tpart_f;
+  unsigned long long* gpw = (unsigned long long*)gpart;      // group values, two words each
   __shared__ unsigned long long sh_t0, sh_pub, sh_jobs;
   __shared__ int sh_stop;
+  __shared__ unsigned long long sh_seq[16];    // job of each wave's tile this round
+  __shared__ int sh_k[16];                     // its tile index in the job (-1: none)
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
   const unsigned long long start = wall_clock64();
+  // the wave's current job (its tiles are mostly consecutive tickets)
+  unsigned long long cs = 0, cjs = 0;
+  int cnt = 0;
+  hipmr_sjob cJ;
   unsigned long long hint = job_base;       // no tile of this wave lies in an earlier job
   while (true) {
     if (threadIdx.x == 0)
@@ -562,7 +616,6 @@ extern "C" __global__ void __launch_bounds__(1024)
             break;
           __builtin_amdgcn_s_sleep(8);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sh_pub = HIPMR_PUB_TILES(v);
         sh_jobs = job_base + HIPMR_PUB_JOBS(v);
         sh_stop = HIPMR_PUB_TILES(v) <= done;   // stopped (or past the deadline) with nothing new
@@ -572,70 +625,128 @@ extern "C" __global__ void __launch_bounds__(1024)
       const unsigned long long pub = sh_pub, njobs = sh_jobs;
       const unsigned long long avail = pub < t0 + 16 ? pub : t0 + 16;
       const unsigned long long T = t0 + w;
+      int myk = -1;
       if (T >= done && T < avail) {
         const unsigned long long G = tile_base + T, fresh = tile_base + pub;
-        // the job holding tile G: the last s in [lo, njobs) whose first tile is <= G.  Slots of
-        // completed jobs below it may already hold jobs published later, whose first tiles are
-        // >= fresh: they count as <= G, which keeps the predicate monotone.
-        unsigned long long lo = hint;
-        if (njobs > HIPMR_RING && njobs - HIPMR_RING > lo) lo = njobs - HIPMR_RING;
-        unsigned long long hi = njobs - 1;
-        while (lo < hi) {
-          const unsigned long long step = (hi - lo + 64) / 64;
-          const unsigned long long cand = lo + (unsigned long long)lane * step;
-          bool pred = false;
-          if (cand <= hi) {
-            const unsigned long long ts = hipmr_ld_agent(dtstart + (cand & (HIPMR_RING - 1)));
-            pred = ts <= G || ts >= fresh;
+        if (!(cnt > 0 && cjs <= G && G < cjs + (unsigned long long)cnt)) {
+          // the job holding tile G: the last s in [lo, njobs) whose first tile is <= G.  Slots of
+          // completed jobs below it may already hold jobs published later, whose first tiles are
+          // >= fresh: they count as <= G, which keeps the predicate monotone.
+          unsigned long long lo = hint;
+          if (njobs > HIPMR_RING && njobs - HIPMR_RING > lo) lo = njobs - HIPMR_RING;
+          unsigned long long hi = njobs - 1;
+          while (lo < hi) {
+            const unsigned long long step = (hi - lo + 64) / 64;
+            const unsigned long long cand = lo + (unsigned long long)lane * step;
+            bool pred = false;
+            if (cand <= hi) {
+              const unsigned long long ts = hipmr_ld_agent(dtstart + (cand & (HIPMR_RING - 1)));
+              pred = ts <= G || ts >= fresh;
+            }
+            const unsigned long long m = __ballot(pred);
+            const int kk = m ? 63 - __builtin_clzll(m) : 0;
+            lo = lo + (unsigned long long)kk * step;
+            hi = lo + step - 1 < hi ? lo + step - 1 : hi;
           }
-          const unsigned long long m = __ballot(pred);
-          const int kk = m ? 63 - __builtin_clzll(m) : 0;
-          lo = lo + (unsigned long long)kk * step;
-          hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+          hint = lo;
+          cs = lo;
+          const unsigned long long slot = lo & (HIPMR_RING - 1);
+          cjs = hipmr_ld_agent(dtstart + slot);
+          cJ = hipmr_job_ld(dring + slot, false);
+          cnt = hipmr_job_ntiles(cJ);
         }
-        hint = lo;
-        const unsigned long long slot = lo & (HIPMR_RING - 1);
-        const hipmr_sjob J = dring[slot];
-        const unsigned long long js = hipmr_ld_agent(dtstart + slot);
-        const int k = (int)(G - js);
-        const float2 r = hipmr_job_dispatch(J, k, lane);
-        const bool mx = J.tmpl == 3;
-        const int ntiles = hipmr_job_ntiles(J), ng = (ntiles + 63) / 64, g = k / 64;
-        const int gsize = ntiles - 64 * g < 64 ? ntiles - 64 * g : 64;
-        unsigned int old = 0;
-        if (lane == 0) {
-          tpart[G & tp_mask] = r;
-          old = __hip_atomic_fetch_add(gdone + slot * 128 + g, 1u, __ATOMIC_ACQ_REL,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-          if (old + 1 == (unsigned)gsize)                  // ready for the slot's next job
+        myk = (int)(G - cjs);
+        const float2 r = hipmr_job_dispatch(cJ, myk, lane);
+        if (lane == 0) hipmr_st_agent(tpart + (G & tp_mask), __builtin_bit_cast(unsigned long long, r));
+      }
+      if (lane == 0) {
+        sh_seq[w] = cs;
+        sh_k[w] = myk;
+      }
+      hipmr_drain();                        // this wave's partial is written
+      __syncthreads();
+      if (w == 0) {
+        // count the round's tiles into their groups: lane l < 16 stands for
+        // wave l's tile; consecutive waves in the same job and group form a
+        // run whose first lane adds the run's length
+        const int k = lane < 16 ? sh_k[lane] : -1;
+        const unsigned long long s = lane < 16 ? sh_seq[lane] : 0;
+        const int g = k >= 0 ? k / 64 : -1;
+        const int kp = lane >= 1 && lane < 16 ? sh_k[lane - 1] : -1;
+        const unsigned long long sp = lane >= 1 && lane < 16 ? sh_seq[lane - 1] : 0;
+        const bool head = k >= 0 && !(kp >= 0 && sp == s && kp / 64 == g);
+        int run = 0;
+        if (head) {
+          run = 1;
+          for (int l2 = lane + 1; l2 < 16; ++l2) {
+            const int k2 = sh_k[l2];
+            if (k2 < 0 || sh_seq[l2] != s || k2 / 64 != g) break;
+            ++run;
+          }
+        }
+        bool full = false;
+        int ntiles_h = 0;
+        if (head) {
+          const unsigned long long slot = s & (HIPMR_RING - 1);
+          const hipmr_sjob Jh = hipmr_job_ld(dring + slot, false);
+          ntiles_h = hipmr_job_ntiles(Jh);
+          const int gsize = ntiles_h - 64 * g < 64 ? ntiles_h - 64 * g : 64;
+          const unsigned int old = __hip_atomic_fetch_add(gdone + slot * 128 + g, (unsigned)run,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          full = old + (unsigned)run == (unsigned)gsize;
+          if (full)                         // ready for the slot's next job
             __hip_atomic_store(gdone + slot * 128 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        old = __shfl(old, 0, 64);
-        if (old + 1 == (unsigned)gsize) {                 // this wave completed group g
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          const double2 gv = hipmr_fin_group(mx, tpart, js + 64ull * g, tp_mask, 0, gsize, lane);
-          double2 tot;
+        // fold every group this round completed, one at a time
+        unsigned long long todo = __ballot(full);
+        while (todo) {
+          const int hl = __builtin_ctzll(todo);
+          todo &= todo - 1;
+          const unsigned long long fs = __shfl(s, hl, 64);
+          const int fg = __shfl(g, hl, 64);
+          const unsigned long long slot = fs & (HIPMR_RING - 1);
+          const hipmr_sjob J = hipmr_job_ld(dring + slot, false);
+          const unsigned long long js = hipmr_ld_agent(dtstart + slot);
+          const int ntiles = hipmr_job_ntiles(J), ng = (ntiles + 63) / 64;
+          const bool mx = J.tmpl == 3;
+          const double2 gv = hipmr_res_group(mx, tpart, js, tp_mask, fg, ntiles, lane);
           bool last = ng == 1;
+          double2 tot = gv;
           if (ng == 1) {
             tot = hipmr_fin_level2(mx, lane == 0, gv, false, gv);
           } else {
+            if (lane == 0) {
+              hipmr_st_agent(gpw + 2 * (slot * 128 + fg), __builtin_bit_cast(unsigned long long, gv.x));
+              hipmr_st_agent(gpw + 2 * (slot * 128 + fg) + 1, __builtin_bit_cast(unsigned long long, gv.y));
+            }
+            hipmr_drain();                  // the group value is written
             unsigned int o2 = 0;
             if (lane == 0) {
-              gpart[slot * 128 + g] = gv;
-              o2 = __hip_atomic_fetch_add(jdone + slot, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+              o2 = __hip_atomic_fetch_add(jdone + slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               if (o2 + 1 == (unsigned)ng)
                 __hip_atomic_store(jdone + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             o2 = __shfl(o2, 0, 64);
             last = o2 + 1 == (unsigned)ng;
             if (last) {
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-              tot = hipmr_fin_groups(mx, gpart + slot * 128, ng, lane);
+              const bool h0 = lane < ng, h1 = lane + 64 < ng;
+              double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+              if (h0) {
+                const unsigned long long* q = gpw + 2 * (slot * 128 + lane);
+                v0 = make_double2(__builtin_bit_cast(double, hipmr_ld_agent(q)),
+                                  __builtin_bit_cast(double, hipmr_ld_agent(q + 1)));
+              }
+              if (h1) {
+                const unsigned long long* q = gpw + 2 * (slot * 128 + lane + 64);
+                v1 = make_double2(__builtin_bit_cast(double, hipmr_ld_agent(q)),
+                                  __builtin_bit_cast(double, hipmr_ld_agent(q + 1)));
+              }
+              tot = hipmr_fin_level2(mx, h0, v0, h1, v1);
             }
           }
           if (last && lane == 0) {
-            hipmr_job_post(J, tot, hr_flags + slot, lo + 1);
-            __hip_atomic_fetch_add(ctrl + 16, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            hipmr_job_post(J, tot, hr_flags + slot, fs + 1);
+            __hip_atomic_fetch_add(ctrl + 16, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }

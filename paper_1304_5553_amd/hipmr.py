@@ -23,7 +23,9 @@ import struct
 import threading
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhipmr.so")
+# HIPMR_LIBRARY names another build of the same library (the sanitizer build
+# the CPU tests can run against); by default the in-tree libhipmr.so
+LIB_PATH = os.environ.get("HIPMR_LIBRARY") or os.path.join(_HERE, "libhipmr.so")
 
 OK = 0
 F32, F64, I8, U8, I16, U16, I32, U32, I64, BF16, F16, FP8, C64 = range(1, 14)

@@ -346,13 +346,14 @@ def test_server_config_validation_without_a_gpu():
 
 
 def test_workspace_sizes_follow_their_documented_rules():
-    # reduce: 64 KiB of block partials plus 256 bytes, whatever n; 0 for an
+    # reduce: 64 KiB of block partials, 32 KiB of the norm's first-pass
+    # partials and 256 bytes for its scale, whatever n; 0 for an
     # elementwise handle.  Segmented: grows with the number of segments and
     # elements (the tile table), never below the plain reduce's partials.
     red = hm.compile("k[i]", "long: const int *k")
     ew = hm.compile("z[i] = x[i]", "float *z, const float *x")
     sizes = {hm.reduce_workspace_bytes(red, n) for n in (0, 1, 1000, 1 << 20, 1 << 28, 1 << 40)}
-    assert sizes == {65536 + 256}
+    assert sizes == {65536 + 32768 + 256}
     assert hm.reduce_workspace_bytes(ew, 1 << 20) == 0
     seg = [hm.segmented_workspace_bytes(red, 4096, n) for n in (0, 1 << 20, 1 << 28)]
     assert seg == sorted(seg) and seg[0] > 0
