@@ -108,9 +108,13 @@ hipmr_status seg_prepare(hipmr_kernel* h, const char* combine, const char* neutr
     }
     bool idx64 = total_n >= (int64_t(1) << 31);
     int lds = cfg.seg_global ? 0 : lds_capacity(nseg);
-    hipmr_status st = variant_function(h, seg_spec(KernelKind::SegPlan, cfg, idx64, combine, neutral, lds),
-                                       &out->plan, syms);
-    if (st != HIPMR_OK) return st;
+    hipmr_status st = HIPMR_OK;
+    out->plan = nullptr;
+    if (lds == 0) {       // the table does not fit LDS: a planning launch writes it to global memory
+        st = variant_function(h, seg_spec(KernelKind::SegPlan, cfg, idx64, combine, neutral, lds),
+                              &out->plan, syms);
+        if (st != HIPMR_OK) return st;
+    }
     st = variant_function(h, seg_spec(KernelKind::SegS1, cfg, idx64, combine, neutral, lds), &out->s1, syms);
     if (st != HIPMR_OK) return st;
     st = variant_function(h, seg_spec(KernelKind::SegS2, cfg, idx64, combine, neutral, lds), &out->s2, syms);
@@ -134,9 +138,12 @@ hipmr_status seg_launch(hipmr_kernel* h, const SegLaunch& L, int32_t nseg, const
     long long cap = max_tiles(nseg, total_n, L.cfg.vec);
     const void* off = d_offsets;
     int ns = nseg;
-    void* p_plan[6] = {&off, &ns, &total, &head, &tile_start, &cap};
-    hipmr_status st = launch(L.plan, 1, kPlanBlock, p_plan, stream);
-    if (st != HIPMR_OK) return st;
+    hipmr_status st = HIPMR_OK;
+    if (L.plan) {
+        void* p_plan[6] = {&off, &ns, &total, &head, &tile_start, &cap};
+        st = launch(L.plan, 1, kPlanBlock, p_plan, stream);
+        if (st != HIPMR_OK) return st;
+    }
     std::vector<void*> p1;
     if (h->prog.sig.args.empty()) p1.push_back(&head);   // hipmr_unused
     for (size_t k = 0; k < h->prog.sig.args.size(); ++k) p1.push_back(args[k]);

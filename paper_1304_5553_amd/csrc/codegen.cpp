@@ -947,38 +947,36 @@ __device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long lo
   const long long t = (b - ab + T - 1) / T;
   return t < 1 ? 1 : (int)t;
 }
-)HIP";
 
-// Planner: tiles per segment and their exclusive prefix, one block.  Each
-// thread takes 4 consecutive segments per round of 4096 (all offset loads
-// issued before any is used).  Counts are summed in 64 bits and every
-// written prefix is capped at the tile capacity of the workspace, so offsets
-// that describe more tiles than it holds (overlapping segments) can never
-// send a later kernel past it.
-const char* kSegPlan = R"HIP(
-extern "C" __global__ void __launch_bounds__(1024)
-@@KNAME@@(const long long* __restrict__ hipmr_off, int hipmr_nseg, long long hipmr_total,
-          long long hipmr_head, int* __restrict__ hipmr_tile_start, long long hipmr_cap)
-{
-  constexpr int B = 1024, R = 4, V = @@VEC@@;
-  constexpr long long T = 64LL * @@VEC@@ * @@IPT@@;
+// The tile table: tiles per segment and their exclusive prefix, by one block
+// of B threads.  Each thread takes R = 4 consecutive segments per round of
+// B * R (all offset loads issued before any is used).  Counts are summed in
+// 64 bits and every entry is capped at the tile capacity of the workspace,
+// so offsets that describe more tiles than it holds (overlapping segments)
+// can never send a later kernel past it.  The table goes to `lds` and / or
+// `glob` (either may be null); it is complete when this returns.
+template <int B>
+__device__ void hipmr_seg_plan(const long long* __restrict__ off, int nseg, long long total,
+                               long long head, int V, long long T, long long cap,
+                               int* lds, int* __restrict__ glob) {
+  constexpr int R = 4;
   __shared__ long long hipmr_wsum[B / 64];
   __shared__ long long hipmr_carry;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (threadIdx.x == 0) hipmr_carry = 0;
   __syncthreads();
-  for (int base = 0; base < hipmr_nseg; base += B * R) {
+  for (int base = 0; base < nseg; base += B * R) {
     const int s0 = base + threadIdx.x * R;
     long long o[R + 1];
 #pragma unroll
-    for (int j = 0; j <= R; ++j) o[j] = s0 + j <= hipmr_nseg ? hipmr_off[s0 + j] : 0;
+    for (int j = 0; j <= R; ++j) o[j] = s0 + j <= nseg ? off[s0 + j] : 0;
     long long t[R], tsum = 0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       t[j] = 0;
-      if (s0 + j < hipmr_nseg) {
+      if (s0 + j < nseg) {
         long long a, b, ab;
-        hipmr_seg_clamp(o[j], o[j + 1], hipmr_total, hipmr_head, V, a, b, ab);
+        hipmr_seg_clamp(o[j], o[j + 1], total, head, V, a, b, ab);
         t[j] = hipmr_seg_tiles(a, b, ab, T);
       }
       tsum += t[j];
@@ -1005,23 +1003,45 @@ extern "C" __global__ void __launch_bounds__(1024)
     long long run = excl;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      if (s0 + j < hipmr_nseg) hipmr_tile_start[s0 + j] = (int)(run < hipmr_cap ? run : hipmr_cap);
+      if (s0 + j < nseg) {
+        const int v = (int)(run < cap ? run : cap);
+        if (lds) lds[s0 + j] = v;
+        if (glob) glob[s0 + j] = v;
+      }
       run += t[j];
     }
     __syncthreads();
-    if (threadIdx.x == B - 1) hipmr_carry = excl + tsum < hipmr_cap ? excl + tsum : hipmr_cap;
+    if (threadIdx.x == B - 1) hipmr_carry = excl + tsum < cap ? excl + tsum : cap;
     __syncthreads();
   }
-  if (threadIdx.x == 0) hipmr_tile_start[hipmr_nseg] = (int)hipmr_carry;
+  if (threadIdx.x == 0) {
+    const int v = (int)hipmr_carry;
+    if (lds) lds[nseg] = v;
+    if (glob) glob[nseg] = v;
+  }
+  __syncthreads();
 }
 )HIP";
 
-// Persistent stage 1: waves take tiles t = wave, wave + nwaves, ...
+// Planner (for tables too large for LDS): the tile table in global memory,
+// one block of 1024 threads.
+const char* kSegPlan = R"HIP(
+extern "C" __global__ void __launch_bounds__(1024)
+@@KNAME@@(const long long* __restrict__ hipmr_off, int hipmr_nseg, long long hipmr_total,
+          long long hipmr_head, int* __restrict__ hipmr_tile_start, long long hipmr_cap)
+{
+  hipmr_seg_plan<1024>(hipmr_off, hipmr_nseg, hipmr_total, hipmr_head, @@VEC@@,
+                       64LL * @@VEC@@ * @@IPT@@, hipmr_cap, nullptr, hipmr_tile_start);
+}
+)HIP";
+
+// Persistent stage 1: waves take tiles t = wave, wave + nwaves, ...  (With
+// the table in LDS this is also the planner: no separate planning launch.)
 const char* kSegS1 = R"HIP(
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_total, long long hipmr_head,
           const long long* __restrict__ hipmr_offsets, int hipmr_nseg,
-          const int* __restrict__ hipmr_tile_start, hipmr_acc* __restrict__ hipmr_tpart,
+          int* __restrict__ hipmr_tile_start, hipmr_acc* __restrict__ hipmr_tpart,
           long long hipmr_cap)
 {
   typedef @@IDX@@ hipmr_idx;
@@ -1031,15 +1051,16 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   const hipmr_idx n = (hipmr_idx)hipmr_total;
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   const int hipmr_lane = threadIdx.x & 63;
-  // the tile-start table, staged in LDS when it fits (checked here as well,
-  // so a table larger than the LDS copy is always read from global memory)
+  // the tile-start table: when it fits LDS every block computes it there
+  // from the offsets (block 0 also writes it to global memory for the
+  // per-segment fold), else the planner has written it to global memory
+  // (checked here as well, so a table larger than the LDS copy is always
+  // read from global memory)
   __shared__ int hipmr_ts_lds[HIPMR_LDS_SEGS > 0 ? HIPMR_LDS_SEGS : 1];
   const bool hipmr_in_lds = HIPMR_LDS_SEGS > 0 && hipmr_nseg < HIPMR_LDS_SEGS;
-  if (hipmr_in_lds) {
-    for (int hipmr_k = threadIdx.x; hipmr_k <= hipmr_nseg; hipmr_k += HIPMR_B)
-      hipmr_ts_lds[hipmr_k] = hipmr_tile_start[hipmr_k];
-    __syncthreads();
-  }
+  if (hipmr_in_lds)
+    hipmr_seg_plan<HIPMR_B>(hipmr_offsets, hipmr_nseg, hipmr_total, hipmr_head, HIPMR_V, HIPMR_T,
+                            hipmr_cap, hipmr_ts_lds, blockIdx.x == 0 ? hipmr_tile_start : nullptr);
   auto hipmr_ts = [&](int hipmr_k) -> int {
     return hipmr_in_lds ? hipmr_ts_lds[hipmr_k] : hipmr_tile_start[hipmr_k];
   };

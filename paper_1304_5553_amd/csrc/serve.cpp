@@ -590,7 +590,9 @@ extern "C" __global__ void __launch_bounds__(1024)
   __shared__ unsigned long long sh_t0, sh_pub, sh_jobs;
   __shared__ int sh_stop;
   __shared__ unsigned long long sh_seq[16];    // job of each wave's tile this round
+  __shared__ unsigned long long sh_js[16];     // that job's first tile
   __shared__ int sh_k[16];                     // its tile index in the job (-1: none)
+  __shared__ float2 sh_part[16];               // the tile's partial
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
   const unsigned long long start = wall_clock64();
@@ -614,7 +616,7 @@ extern "C" __global__ void __launch_bounds__(1024)
           if (hipmr_ld_agent(rep + 2) != 0 || wall_clock64() - start > deadline + deadline / 8 ||
               iter > HIPMR_MAX_POLLS)
             break;
-          __builtin_amdgcn_s_sleep(8);
+          __builtin_amdgcn_s_sleep(2);
         }
         sh_pub = HIPMR_PUB_TILES(v);
         sh_jobs = job_base + HIPMR_PUB_JOBS(v);
@@ -626,6 +628,7 @@ extern "C" __global__ void __launch_bounds__(1024)
       const unsigned long long avail = pub < t0 + 16 ? pub : t0 + 16;
       const unsigned long long T = t0 + w;
       int myk = -1;
+      float2 r = make_float2(0.0f, 0.0f);
       if (T >= done && T < avail) {
         const unsigned long long G = tile_base + T, fresh = tile_base + pub;
         if (!(cnt > 0 && cjs <= G && G < cjs + (unsigned long long)cnt)) {
@@ -636,17 +639,26 @@ extern "C" __global__ void __launch_bounds__(1024)
           if (njobs > HIPMR_RING && njobs - HIPMR_RING > lo) lo = njobs - HIPMR_RING;
           unsigned long long hi = njobs - 1;
           while (lo < hi) {
+            // lane 63 checks the newest job first: under light load the tile is usually its
             const unsigned long long step = (hi - lo + 64) / 64;
-            const unsigned long long cand = lo + (unsigned long long)lane * step;
+            const unsigned long long cand = lane == 63 ? hi : lo + (unsigned long long)lane * step;
             bool pred = false;
             if (cand <= hi) {
               const unsigned long long ts = hipmr_ld_agent(dtstart + (cand & (HIPMR_RING - 1)));
               pred = ts <= G || ts >= fresh;
             }
             const unsigned long long m = __ballot(pred);
-            const int kk = m ? 63 - __builtin_clzll(m) : 0;
-            lo = lo + (unsigned long long)kk * step;
-            hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+            if (m >> 63) {                  // the newest job holds the tile
+              lo = hi;
+              break;
+            }
+            // else lanes 0..62 split [lo, hi - 1]; lane 62's share runs to hi - 1
+            const unsigned long long m62 = m & ((1ull << 63) - 1);
+            const int kk = m62 ? 63 - __builtin_clzll(m62) : 0;
+            const unsigned long long nlo = lo + (unsigned long long)kk * step;
+            const unsigned long long nhi = kk == 62 ? hi - 1 : nlo + step - 1;
+            lo = nlo;
+            hi = nhi < hi - 1 ? nhi : hi - 1;
           }
           hint = lo;
           cs = lo;
@@ -656,12 +668,14 @@ extern "C" __global__ void __launch_bounds__(1024)
           cnt = hipmr_job_ntiles(cJ);
         }
         myk = (int)(G - cjs);
-        const float2 r = hipmr_job_dispatch(cJ, myk, lane);
+        r = hipmr_job_dispatch(cJ, myk, lane);
         if (lane == 0) hipmr_st_agent(tpart + (G & tp_mask), __builtin_bit_cast(unsigned long long, r));
       }
       if (lane == 0) {
         sh_seq[w] = cs;
+        sh_js[w] = cjs;
         sh_k[w] = myk;
+        sh_part[w] = r;
       }
       hipmr_drain();                        // this wave's partial is written
       __syncthreads();
@@ -684,18 +698,24 @@ extern "C" __global__ void __launch_bounds__(1024)
             ++run;
           }
         }
-        bool full = false;
-        int ntiles_h = 0;
+        bool full = false, local = false;
+        unsigned long long jw[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the head lane's job descriptor
         if (head) {
           const unsigned long long slot = s & (HIPMR_RING - 1);
           const hipmr_sjob Jh = hipmr_job_ld(dring + slot, false);
-          ntiles_h = hipmr_job_ntiles(Jh);
+          __builtin_memcpy(jw, &Jh, sizeof(Jh));
+          const int ntiles_h = hipmr_job_ntiles(Jh);
           const int gsize = ntiles_h - 64 * g < 64 ? ntiles_h - 64 * g : 64;
-          const unsigned int old = __hip_atomic_fetch_add(gdone + slot * 128 + g, (unsigned)run,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          full = old + (unsigned)run == (unsigned)gsize;
-          if (full)                         // ready for the slot's next job
-            __hip_atomic_store(gdone + slot * 128 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (run == gsize) {
+            // the whole group is in this round: no other block holds any of its tiles
+            full = local = true;
+          } else {
+            const unsigned int old = __hip_atomic_fetch_add(gdone + slot * 128 + g, (unsigned)run,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            full = old + (unsigned)run == (unsigned)gsize;
+            if (full)                       // ready for the slot's next job
+              __hip_atomic_store(gdone + slot * 128 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
         }
         // fold every group this round completed, one at a time
         unsigned long long todo = __ballot(full);
@@ -704,12 +724,28 @@ extern "C" __global__ void __launch_bounds__(1024)
           todo &= todo - 1;
           const unsigned long long fs = __shfl(s, hl, 64);
           const int fg = __shfl(g, hl, 64);
+          const bool flocal = __shfl((int)local, hl, 64) != 0;
+          unsigned long long fw[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) fw[q] = __shfl(jw[q], hl, 64);
+          hipmr_sjob J;
+          __builtin_memcpy(&J, fw, sizeof(J));
           const unsigned long long slot = fs & (HIPMR_RING - 1);
-          const hipmr_sjob J = hipmr_job_ld(dring + slot, false);
-          const unsigned long long js = hipmr_ld_agent(dtstart + slot);
+          const unsigned long long js = sh_js[hl];
           const int ntiles = hipmr_job_ntiles(J), ng = (ntiles + 63) / 64;
           const bool mx = J.tmpl == 3;
-          const double2 gv = hipmr_res_group(mx, tpart, js, tp_mask, fg, ntiles, lane);
+          double2 gv;
+          if (flocal) {                     // the group's partials are this block's: from LDS
+            const int gsize = ntiles - 64 * fg < 64 ? ntiles - 64 * fg : 64;
+            double2 v = hipmr_fin_neutral(mx);
+            if (lane < gsize) {
+              const float2 p2 = sh_part[hl + lane];
+              v = make_double2((double)p2.x, (double)p2.y);
+            }
+            gv = hipmr_fin_wave(mx, v);
+          } else {
+            gv = hipmr_res_group(mx, tpart, js, tp_mask, fg, ntiles, lane);
+          }
           bool last = ng == 1;
           double2 tot = gv;
           if (ng == 1) {
