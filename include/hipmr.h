@@ -319,11 +319,14 @@ size_t hipmr_segmented_workspace_bytes(hipmr_handle h, int32_t nseg, int64_t tot
  *   cfg:       NULL (the default geometry) or a geometry; with HIPMR_CFG_TUNED
  *              the one hipmr_autotune_segmented stored for this handle,
  *              combine_op, neutral and size class, if any.
- * Three launches on stream: a one-block planner turns the offsets into tiles
- * (tile 0 of a segment holds its unaligned head and up to T body elements,
- * later tiles T elements, T = 64 * vec * items_per_thread); a persistent
- * kernel whose waves each reduce one tile at a time into a tile partial; one
- * wave per segment folding its tiles in order.  A segment's result depends
+ * Two launches on stream (three above 8191 segments): the offsets become a
+ * tile table (tile 0 of a segment holds its unaligned head and up to T body
+ * elements, later tiles T elements, T = 64 * vec * items_per_thread); a
+ * persistent kernel whose waves each reduce one tile at a time into a tile
+ * partial; one wave per segment folding its tiles in order.  Up to 8191
+ * segments every block of the persistent kernel computes the table in LDS
+ * itself (block 0 also writes it to the workspace); above that a one-block
+ * planner launch writes it to the workspace first.  A segment's result depends
  * only on its own bounds and the geometry, so it is bitwise the same whatever
  * the other segments are.  Everything stays on the device, so the sequence
  * can be captured once and replayed with new offset values.

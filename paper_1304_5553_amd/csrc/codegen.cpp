@@ -949,19 +949,19 @@ __device__ __forceinline__ int hipmr_seg_tiles(long long a, long long b, long lo
 }
 
 // The tile table: tiles per segment and their exclusive prefix, by one block
-// of B threads.  Each thread takes R = 4 consecutive segments per round of
+// of B threads.  Each thread takes R consecutive segments per round of
 // B * R (all offset loads issued before any is used).  Counts are summed in
 // 64 bits and every entry is capped at the tile capacity of the workspace,
 // so offsets that describe more tiles than it holds (overlapping segments)
 // can never send a later kernel past it.  The table goes to `lds` and / or
 // `glob` (either may be null); it is complete when this returns.
-template <int B>
+template <int B, int R = 4>
 __device__ void hipmr_seg_plan(const long long* __restrict__ off, int nseg, long long total,
                                long long head, int V, long long T, long long cap,
                                int* lds, int* __restrict__ glob) {
-  constexpr int R = 4;
   __shared__ long long hipmr_wsum[B / 64];
   __shared__ long long hipmr_carry;
+  const auto hipmr_plus = [](long long p, long long q) { return p + q; };
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (threadIdx.x == 0) hipmr_carry = 0;
   __syncthreads();
@@ -981,21 +981,11 @@ __device__ void hipmr_seg_plan(const long long* __restrict__ off, int nseg, long
       }
       tsum += t[j];
     }
-    long long x = tsum;                          // inclusive scan in the wave
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const long long y = __shfl_up(x, d, 64);
-      if (l >= d) x += y;
-    }
+    const long long x = hipmr_dpp_scan(tsum, 0LL, hipmr_plus);   // inclusive scan in the wave
     if (l == 63) hipmr_wsum[w] = x;
     __syncthreads();
     if (w == 0) {                                // scan of the wave totals
-      long long v = l < B / 64 ? hipmr_wsum[l] : 0;
-#pragma unroll
-      for (int d = 1; d < B / 64; d <<= 1) {
-        const long long y = __shfl_up(v, d, 64);
-        if (l >= d) v += y;
-      }
+      const long long v = hipmr_dpp_scan(l < B / 64 ? hipmr_wsum[l] : 0LL, 0LL, hipmr_plus);
       if (l < B / 64) hipmr_wsum[l] = v;
     }
     __syncthreads();
@@ -1037,7 +1027,24 @@ extern "C" __global__ void __launch_bounds__(1024)
 
 // Persistent stage 1: waves take tiles t = wave, wave + nwaves, ...  (With
 // the table in LDS this is also the planner: no separate planning launch.)
+// Per tile, every load is issued before any result is used: the head and
+// tail elements, then the body chunks; the next tile's segment is found (in
+// the table) and its offsets fetched while they are in flight.  The wave's
+// fold is a DPP scan whose last lane holds the tile partial.
 const char* kSegS1 = R"HIP(
+__device__ __forceinline__ hipmr_acc hipmr_wave_total(hipmr_acc v, hipmr_acc e, int lane) {
+  if constexpr (sizeof(hipmr_acc) == 4 || sizeof(hipmr_acc) == 8) {
+    return hipmr_dpp_scan(v, e, [](hipmr_acc a, hipmr_acc b) { return hipmr_combine(a, b); });
+  } else {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const hipmr_acc y = __shfl_up(v, d, 64);
+      if (lane >= d) v = hipmr_combine(y, v);
+    }
+    return v;
+  }
+}
+
 extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 @@KNAME@@(@@PARAMS@@, long long hipmr_total, long long hipmr_head,
           const long long* __restrict__ hipmr_offsets, int hipmr_nseg,
@@ -1051,22 +1058,23 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   const hipmr_idx n = (hipmr_idx)hipmr_total;
   const hipmr_acc hipmr_neutral = (hipmr_acc)(@@NEUTRAL@@);
   const int hipmr_lane = threadIdx.x & 63;
-  // the tile-start table: when it fits LDS every block computes it there
-  // from the offsets (block 0 also writes it to global memory for the
-  // per-segment fold), else the planner has written it to global memory
-  // (checked here as well, so a table larger than the LDS copy is always
-  // read from global memory)
-  __shared__ int hipmr_ts_lds[HIPMR_LDS_SEGS > 0 ? HIPMR_LDS_SEGS : 1];
-  const bool hipmr_in_lds = HIPMR_LDS_SEGS > 0 && hipmr_nseg < HIPMR_LDS_SEGS;
-  if (hipmr_in_lds)
+  // the tile-start table: a variant with LDS room computes it there in
+  // every block (block 0 also writes it to global memory for the
+  // per-segment fold); otherwise the planner has written it to global
+  // memory.  (The host picks the LDS variant only when the table fits.)
+  const int* hipmr_tab;
+  if constexpr (HIPMR_LDS_SEGS > 0) {
+    __shared__ int hipmr_ts_lds[HIPMR_LDS_SEGS > 0 ? HIPMR_LDS_SEGS : 1];
+    if (hipmr_nseg >= HIPMR_LDS_SEGS) return;
     hipmr_seg_plan<HIPMR_B>(hipmr_offsets, hipmr_nseg, hipmr_total, hipmr_head, HIPMR_V, HIPMR_T,
                             hipmr_cap, hipmr_ts_lds, blockIdx.x == 0 ? hipmr_tile_start : nullptr);
-  auto hipmr_ts = [&](int hipmr_k) -> int {
-    return hipmr_in_lds ? hipmr_ts_lds[hipmr_k] : hipmr_tile_start[hipmr_k];
-  };
+    hipmr_tab = hipmr_ts_lds;
+  } else {
+    hipmr_tab = hipmr_tile_start;
+  }
   // the planner caps the table at the workspace's tile capacity; the cap is
   // applied here again so that no tile partial is written past it
-  const int hipmr_total_tiles = hipmr_ts(hipmr_nseg) < hipmr_cap ? hipmr_ts(hipmr_nseg) : (int)hipmr_cap;
+  const int hipmr_total_tiles = hipmr_tab[hipmr_nseg] < hipmr_cap ? hipmr_tab[hipmr_nseg] : (int)hipmr_cap;
   const int hipmr_nwaves = gridDim.x * (HIPMR_B / 64);
   // segment of a tile: the last s with tile_start[s] <= tile (64-way ballot search)
   auto hipmr_find = [&](int hipmr_tile) -> int {
@@ -1074,7 +1082,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
     while (hipmr_lo < hipmr_hi) {
       const int hipmr_step = (hipmr_hi - hipmr_lo + 64) / 64;
       const int hipmr_cand = hipmr_lo + hipmr_lane * hipmr_step;
-      const bool hipmr_pred = hipmr_cand <= hipmr_hi && hipmr_ts(hipmr_cand) <= hipmr_tile;
+      const bool hipmr_pred = hipmr_cand <= hipmr_hi && hipmr_tab[hipmr_cand] <= hipmr_tile;
       const unsigned long long hipmr_m = __ballot(hipmr_pred);
       const int hipmr_k = 63 - __builtin_clzll(hipmr_m);
       hipmr_lo = hipmr_lo + hipmr_k * hipmr_step;
@@ -1083,8 +1091,6 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
     return hipmr_lo;
   };
   int hipmr_t = blockIdx.x * (HIPMR_B / 64) + (threadIdx.x >> 6);
-  // the segment and raw bounds of the wave's next tile are fetched while the
-  // current tile's loads are in flight
   int hipmr_s = 0;
   long long hipmr_oa = 0, hipmr_ob = 0;
   if (hipmr_t < hipmr_total_tiles) {
@@ -1095,26 +1101,43 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
   for (; hipmr_t < hipmr_total_tiles; hipmr_t += hipmr_nwaves) {
     long long hipmr_sa, hipmr_sb, hipmr_sab;
     hipmr_seg_clamp(hipmr_oa, hipmr_ob, hipmr_total, hipmr_head, HIPMR_V, hipmr_sa, hipmr_sb, hipmr_sab);
-    const long long hipmr_k = hipmr_t - hipmr_ts(hipmr_s);
+    const long long hipmr_k = hipmr_t - hipmr_tab[hipmr_s];
     const long long hipmr_tstart = hipmr_k == 0 ? hipmr_sa : hipmr_sab + hipmr_k * HIPMR_T;
     const long long hipmr_hend = hipmr_k == 0 ? hipmr_sab : hipmr_tstart;
     const long long hipmr_te = hipmr_sab + (hipmr_k + 1) * HIPMR_T < hipmr_sb ? hipmr_sab + (hipmr_k + 1) * HIPMR_T : hipmr_sb;
     const long long hipmr_nch = hipmr_te > hipmr_hend ? (hipmr_te - hipmr_hend) / HIPMR_V : 0;
     const long long hipmr_tail = hipmr_hend + hipmr_nch * HIPMR_V;
+    // the unaligned head (tile 0 only) and the ragged tail, one element per lane
+    hipmr_acc hipmr_hv = hipmr_neutral, hipmr_tv = hipmr_neutral;
+    const bool hipmr_in_head = hipmr_lane < hipmr_hend - hipmr_tstart;
+    const bool hipmr_in_tail = hipmr_lane < hipmr_te - hipmr_tail;
+    if (hipmr_in_head) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_tstart + hipmr_lane);
+      hipmr_hv = (hipmr_acc)(@@MAP@@);
+    }
+    if (hipmr_in_tail) {
+      const hipmr_idx i = (hipmr_idx)(hipmr_tail + hipmr_lane);
+      hipmr_tv = (hipmr_acc)(@@MAP@@);
+    }
     hipmr_acc hipmr_a[HIPMR_U];
 #pragma unroll
     for (int u = 0; u < HIPMR_U; ++u) hipmr_a[u] = hipmr_neutral;
-    if (hipmr_lane < hipmr_hend - hipmr_tstart) {
-      const hipmr_idx i = (hipmr_idx)(hipmr_tstart + hipmr_lane);
-      hipmr_a[0] = hipmr_combine(hipmr_a[0], (hipmr_acc)(@@MAP@@));
-    }
     @@DECL_PACKS@@
+    const bool hipmr_full = hipmr_nch == 64LL * HIPMR_U;   // every lane has all U chunks
+    if (hipmr_full) {
 #pragma unroll
-    for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
-      const long long hipmr_c = hipmr_lane + 64 * hipmr_u;
-      if (hipmr_c < hipmr_nch) {
-        const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_off = hipmr_hend + (hipmr_lane + 64LL * hipmr_u) * HIPMR_V;
         @@LOADS@@
+      }
+    } else {
+#pragma unroll
+      for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
+        const long long hipmr_c = hipmr_lane + 64 * hipmr_u;
+        if (hipmr_c < hipmr_nch) {
+          const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
+          @@LOADS@@
+        }
       }
     }
     const int hipmr_tn = hipmr_t + hipmr_nwaves;
@@ -1126,7 +1149,7 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 #pragma unroll
     for (int hipmr_u = 0; hipmr_u < HIPMR_U; ++hipmr_u) {
       const long long hipmr_c = hipmr_lane + 64 * hipmr_u;
-      if (hipmr_c < hipmr_nch) {
+      if (hipmr_full || hipmr_c < hipmr_nch) {
         const long long hipmr_off = hipmr_hend + hipmr_c * HIPMR_V;
 #pragma unroll
         for (int hipmr_j = 0; hipmr_j < HIPMR_V; ++hipmr_j) {
@@ -1135,13 +1158,13 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
         }
       }
     }
-    if (hipmr_lane < hipmr_te - hipmr_tail) {
-      const hipmr_idx i = (hipmr_idx)(hipmr_tail + hipmr_lane);
-      hipmr_a[HIPMR_U - 1] = hipmr_combine(hipmr_a[HIPMR_U - 1], (hipmr_acc)(@@MAP@@));
-    }
+    // the head joins on the left of the body it precedes (combined only
+    // now, so that no wait for its load comes before the body's loads)
+    if (hipmr_in_head) hipmr_a[0] = hipmr_combine(hipmr_hv, hipmr_a[0]);
+    if (hipmr_in_tail) hipmr_a[HIPMR_U - 1] = hipmr_combine(hipmr_a[HIPMR_U - 1], hipmr_tv);
     hipmr_acc hipmr_r = hipmr_fold<HIPMR_U>(hipmr_a);
-    hipmr_r = hipmr_block_reduce<64>(hipmr_r, hipmr_neutral);
-    if (hipmr_lane == 0) hipmr_tpart[hipmr_t] = hipmr_r;
+    hipmr_r = hipmr_wave_total(hipmr_r, hipmr_neutral, hipmr_lane);
+    if (hipmr_lane == 63) hipmr_tpart[hipmr_t] = hipmr_r;
   }
 }
 )HIP";
@@ -1182,10 +1205,11 @@ extern "C" __global__ void __launch_bounds__(@@BLOCK@@)
 // wave's range; pass 2 (one block) scans the wave totals; pass 3 rescans each
 // range from its wave prefix.  The order of every combination is a fixed
 // function of n and the geometry.
-const char* kScanHelpers = R"HIP(
-// Data-parallel-primitive (DPP) lane moves on 32-bit halves: lanes whose
-// source lies outside the pattern (or whose row is masked off) receive
-// `fill`.
+// Data-parallel-primitive (DPP) lane moves and the inclusive wave scan built
+// from them (shared by the segmented and scan kernels).
+const char* kDppHelpers = R"HIP(
+// DPP lane moves on 32-bit halves: lanes whose source lies outside the
+// pattern (or whose row is masked off) receive `fill`.
 template <int CTRL, int ROWS, typename T>
 __device__ __forceinline__ T hipmr_dpp(T v, T fill) {
   if constexpr (sizeof(T) == 4) {
@@ -1201,19 +1225,28 @@ __device__ __forceinline__ T hipmr_dpp(T v, T fill) {
   }
 }
 
-// inclusive scan across the wave (lane l receives v_0 (+) ... (+) v_l):
-// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the totals of
-// row 0 / rows 0-1 broadcast into the rows after them
+// inclusive scan across the wave of a 4- or 8-byte value under op (lane l
+// receives v_0 op ... op v_l, the earlier lanes always on the left): shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then the totals of row 0 /
+// rows 0-1 broadcast into the rows after them; e is op's neutral element
+template <typename T, typename Op>
+__device__ __forceinline__ T hipmr_dpp_scan(T v, T e, Op op) {
+  v = op(hipmr_dpp<0x111, 0xf>(v, e), v);     // row_shr:1
+  v = op(hipmr_dpp<0x112, 0xf>(v, e), v);     // row_shr:2
+  v = op(hipmr_dpp<0x114, 0xf>(v, e), v);     // row_shr:4
+  v = op(hipmr_dpp<0x118, 0xf>(v, e), v);     // row_shr:8
+  v = op(hipmr_dpp<0x142, 0xa>(v, e), v);     // row_bcast:15 into rows 1, 3
+  v = op(hipmr_dpp<0x143, 0xc>(v, e), v);     // row_bcast:31 into rows 2, 3
+  return v;
+}
+)HIP";
+
+const char* kScanHelpers = R"HIP(
+// inclusive scan across the wave (lane l receives v_0 (+) ... (+) v_l)
 template <typename T>
 __device__ __forceinline__ T hipmr_wave_scan(T v, int lane, T e) {
   if constexpr (sizeof(T) == 4 || sizeof(T) == 8) {
-    v = hipmr_combine(hipmr_dpp<0x111, 0xf>(v, e), v);     // row_shr:1
-    v = hipmr_combine(hipmr_dpp<0x112, 0xf>(v, e), v);     // row_shr:2
-    v = hipmr_combine(hipmr_dpp<0x114, 0xf>(v, e), v);     // row_shr:4
-    v = hipmr_combine(hipmr_dpp<0x118, 0xf>(v, e), v);     // row_shr:8
-    v = hipmr_combine(hipmr_dpp<0x142, 0xa>(v, e), v);     // row_bcast:15 into rows 1, 3
-    v = hipmr_combine(hipmr_dpp<0x143, 0xc>(v, e), v);     // row_bcast:31 into rows 2, 3
-    return v;
+    return hipmr_dpp_scan(v, e, [](T a, T b) { return hipmr_combine(a, b); });
   } else {
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -1612,6 +1645,7 @@ std::string render(const Program& prog, const KernelSpec& spec, std::string* sym
         src << kReduceHelpers;
     }
     if (comp) src << kCompHelpers;
+    if (seg || scan) src << kDppHelpers;
     if (seg) src << kSegHelpers;
     if (scan) src << kScanHelpers;
     if (shifts) src << kShiftHelpers;
