@@ -54,6 +54,8 @@ constexpr int kOneLaunchTiles = 16;      // a job of at most this many tiles alo
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
 constexpr int kMaxJobTiles = 8192;       // tiles of one job (its fold has at most 128 groups)
 constexpr int kRing = 4096;               // resident: job descriptors in flight (power of two)
+constexpr int kRingWords = 16;            // resident: 64-bit words per host ring slot (nine used)
+constexpr uint64_t kField = (1ull << 48) - 1;   // resident: a ring word's payload
 constexpr size_t kCtrlBytes = 4096;       // resident: control words (zeroed before each launch)
 constexpr int64_t kRotateNs = 250000000;  // resident: a new instance every 250 ms of service
 constexpr int64_t kIdleStopNs = 10000000; // resident: the instance stops after 10 ms without jobs
@@ -286,16 +288,21 @@ __device__ __forceinline__ double2 hipmr_fin_groups(bool mx, const double2* gv, 
 
 // The job's result from its total (square root of the norm, ratio of the
 // weighted mean), written before the job's completion flag (in host memory)
-// changes.
+// changes.  The result goes out as a system-scope store, which completes
+// only once it is visible to the whole system, so waiting for it (rather
+// than a system-scope fence, which writes back the whole L2) orders it
+// before the flag.
 __device__ __forceinline__ void hipmr_job_post(const hipmr_sjob& J, double2 tot,
                                                unsigned long long* flag, unsigned long long seq) {
   double r = tot.x;
   if (J.tmpl == 2) r = sqrt(r);
   else if (J.tmpl == 7) r = r / tot.y;
-  *J.out = r;
-  // the result is visible system-wide before the completion flag changes
-  __threadfence_system();
-  *(volatile unsigned long long*)flag = seq;
+  __hip_atomic_store((unsigned long long*)J.out, __builtin_bit_cast(unsigned long long, r), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __hip_atomic_store(flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The fold of the partials [t0, t1) by one block of 1024 threads: wave w
@@ -428,8 +435,15 @@ extern "C" __global__ void __launch_bounds__(1024)
 // ---------------------------------------------------------------- resident
 // One kernel that stays on the device and takes jobs from a ring of
 // descriptors in mapped host memory, so a job costs no launch.
-//   Host ring (mapped host memory): hdr[0] = jobs published (job s sits in
-//   slot s % R of hr_jobs, its first tile's global index in hr_tstart);
+//   Host ring (mapped host memory): job s sits in slot s % R of hr_words as
+//   nine 64-bit words (x, y, w, n, out, tmpl | dtype << 8 | head << 16 |
+//   epoch << 32 (head a signed 16-bit field, epoch the low 16 bits of the
+//   instance the job was written for), a, b, its first tile's global
+//   index), each a 48-bit field under a 16-bit
+//   tag of its lap of the ring ((s / R + 1) mod 2^16): one read of the nine
+//   words finds a job complete when every word carries its lap's tag, so
+//   the dispatcher needs no separate published count (and no second trip
+//   over PCIe);
 //   hdr[16] = epoch << 44 | the job index at which instance `epoch` stops
 //   accepting (a word naming another epoch does not stop this one); the
 //   dispatcher writes hdr[32] = epoch << 44 | (jobs accepted + 1) as it
@@ -503,8 +517,14 @@ __device__ __forceinline__ int hipmr_job_ntiles(const hipmr_sjob& J) {
 #define HIPMR_MAX_POLLS (1ull << 25)   // polls per wait, whatever the clock says
 #define HIPMR_PUB_JOBS(v) ((v) >> 40)
 
-__device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __restrict__ hr_jobs,
-                                   const unsigned long long* __restrict__ hr_tstart,
+#define HIPMR_RING_WORDS @@RING_WORDS@@            // words per host ring slot (nine used)
+#define HIPMR_FIELD ((1ull << 48) - 1)
+
+__device__ __forceinline__ unsigned long long hipmr_ring_tag(unsigned long long s) {
+  return ((s / HIPMR_RING) + 1) & 0xffffull;
+}
+
+__device__ void hipmr_res_dispatch(unsigned long long* hdr, const unsigned long long* __restrict__ hr_words,
                                    unsigned long long* ctrl, hipmr_sjob* dring,
                                    unsigned long long* dtstart, unsigned long long job_base,
                                    unsigned long long tile_base, unsigned long long epoch,
@@ -513,26 +533,59 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __
   const unsigned long long t0 = wall_clock64();
   unsigned long long seq = job_base, stop_at = ~0ull;
   bool closing = false;
+  // lanes 0..62 read word lane % 9 of slot seq + lane / 9 (seven slots per
+  // read), lane 63 the stop word: one trip over PCIe per pass
+  const int js = lane / 9, jw = lane % 9;
   // a second bound besides the clock: every pass takes at least one read of
   // host memory (about a microsecond)
   for (unsigned long long iter = 0;; ++iter) {
     if (!closing) {
-      const unsigned long long P = hipmr_ld_sys(hdr);
-      const unsigned long long Sw = hipmr_ld_sys(hdr + 16);
+      const unsigned long long v =
+          lane < 63 ? hipmr_ld_sys(hr_words + ((seq + js) & (HIPMR_RING - 1)) * HIPMR_RING_WORDS + jw)
+                    : hipmr_ld_sys(hdr + 16);
+      const unsigned long long Sw = __shfl(v, 63, 64);
       // the stop word names the instance it is for (epoch << 44 | job index)
       const unsigned long long S = (Sw >> 44) == (epoch & ((1ull << 20) - 1)) ? (Sw & ((1ull << 44) - 1))
                                                                              : ~0ull;
-      const unsigned long long lim = P < S ? P : S;
-      if (lim > seq) {
-        const int cnt = lim - seq < 64 ? (int)(lim - seq) : 64;
+      const unsigned long long m = __ballot(lane < 63 && (v >> 48) == hipmr_ring_tag(seq + js));
+      // the instance each job was written for (word 5, bits 32..47): a job
+      // of another instance ends this one's jobs, whatever the order in
+      // which the reads above saw the ring and the stop word
+      const unsigned long long mine =
+          __ballot(lane < 63 && jw == 5 && ((v >> 32) & 0xffffull) == (epoch & 0xffffull));
+      int cnt = 0;                                     // complete slots of this instance from seq on
+      bool other = false;                              // the next complete slot is another instance's
+      while (cnt < 7 && ((m >> (9 * cnt)) & 0x1ffull) == 0x1ffull) {
+        if (!((mine >> (9 * cnt + 5)) & 1ull)) {
+          other = true;
+          break;
+        }
+        ++cnt;
+      }
+      if (S > seq && (unsigned long long)cnt > S - seq) cnt = (int)(S - seq);
+      if (S <= seq) cnt = 0;
+      if (cnt > 0) {
+        unsigned long long f[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) f[k] = __shfl(v & HIPMR_FIELD, 9 * (lane < cnt ? lane : 0) + k, 64);
         unsigned long long tend = 0;
         if (lane < cnt) {
-          const unsigned long long s = seq + lane, slot = s & (HIPMR_RING - 1);
-          const hipmr_sjob J = hipmr_job_ld(hr_jobs + slot, true);
-          const unsigned long long ts = hipmr_ld_sys(hr_tstart + slot);
+          const unsigned long long slot = (seq + lane) & (HIPMR_RING - 1);
+          hipmr_sjob J;
+          J.x = (const void*)f[0];
+          J.y = (const void*)f[1];
+          J.w = (const void*)f[2];
+          J.n = (long long)f[3];
+          J.out = (double*)f[4];
+          J.tmpl = (int)(f[5] & 0xff);
+          J.dtype = (int)((f[5] >> 8) & 0xff);
+          J.head = (int)(short)(unsigned short)((f[5] >> 16) & 0xffff);   // signed: -1 = no common alignment
+          J.tile0 = 0;
+          J.a = __uint_as_float((unsigned)f[6]);
+          J.b = __uint_as_float((unsigned)f[7]);
           hipmr_job_st(dring + slot, J);
-          hipmr_st_agent(dtstart + slot, ts);
-          tend = ts + (unsigned long long)hipmr_job_ntiles(J);
+          hipmr_st_agent(dtstart + slot, f[8]);
+          tend = f[8] + (unsigned long long)hipmr_job_ntiles(J);
         }
         tend = __shfl(tend, cnt - 1, 64);
         seq += cnt;
@@ -541,7 +594,7 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const hipmr_sjob* __
           hipmr_st_agent(ctrl + 32 + 16 * lane, ((seq - job_base) << 40) | (tend - tile_base));
         continue;
       }
-      if (S <= seq) {
+      if (S <= seq || other) {
         closing = true;
         stop_at = seq;
       }
@@ -572,8 +625,8 @@ __device__ __forceinline__ double2 hipmr_res_group(bool mx, const unsigned long 
 }
 
 extern "C" __global__ void __launch_bounds__(1024)
-@@PREFIX@@_res(unsigned long long* hdr, const hipmr_sjob* __restrict__ hr_jobs,
-               const unsigned long long* __restrict__ hr_tstart, unsigned long long* hr_flags,
+@@PREFIX@@_res(unsigned long long* hdr, const unsigned long long* __restrict__ hr_words,
+               unsigned long long* hr_flags,
                unsigned long long* ctrl, hipmr_sjob* dring, unsigned long long* dtstart,
                unsigned int* gdone, unsigned int* jdone, double2* gpart, float2* tpart_f,
                unsigned long long tp_mask, unsigned long long job_base, unsigned long long tile_base,
@@ -581,8 +634,7 @@ extern "C" __global__ void __launch_bounds__(1024)
 {
   if (blockIdx.x == 0) {
     if (threadIdx.x < 64)
-      hipmr_res_dispatch(hdr, hr_jobs, hr_tstart, ctrl, dring, dtstart, job_base, tile_base, epoch,
-                         deadline);
+      hipmr_res_dispatch(hdr, hr_words, ctrl, dring, dtstart, job_base, tile_base, epoch, deadline);
     return;
   }
   unsigned long long* tpart = (unsigned long long*)tpart_f;
@@ -593,6 +645,7 @@ extern "C" __global__ void __launch_bounds__(1024)
   __shared__ unsigned long long sh_js[16];     // that job's first tile
   __shared__ int sh_k[16];                     // its tile index in the job (-1: none)
   __shared__ float2 sh_part[16];               // the tile's partial
+  __shared__ hipmr_sjob sh_job[16];            // that job's descriptor
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
   const unsigned long long start = wall_clock64();
@@ -676,6 +729,7 @@ extern "C" __global__ void __launch_bounds__(1024)
         sh_js[w] = cjs;
         sh_k[w] = myk;
         sh_part[w] = r;
+        if (myk >= 0) sh_job[w] = cJ;
       }
       hipmr_drain();                        // this wave's partial is written
       __syncthreads();
@@ -702,7 +756,7 @@ extern "C" __global__ void __launch_bounds__(1024)
         unsigned long long jw[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the head lane's job descriptor
         if (head) {
           const unsigned long long slot = s & (HIPMR_RING - 1);
-          const hipmr_sjob Jh = hipmr_job_ld(dring + slot, false);
+          const hipmr_sjob Jh = sh_job[lane];     // the job's descriptor, as the wave read it
           __builtin_memcpy(jw, &Jh, sizeof(Jh));
           const int ntiles_h = hipmr_job_ntiles(Jh);
           const int gsize = ntiles_h - 64 * g < 64 ? ntiles_h - 64 * g : 64;
@@ -907,6 +961,7 @@ std::string serve_source(const std::string& prefix) {
     rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
     rep("@@NINLINE@@", std::to_string(kInlineJobs));
     rep("@@RING@@", std::to_string(kRing));
+    rep("@@RING_WORDS@@", std::to_string(kRingWords));
     return src;
 }
 
@@ -935,11 +990,10 @@ struct hipmr_server {
     // parts, and the state of the instance on the device
     struct Res {
         hipStream_t stream = nullptr;
-        uint64_t* hdr = nullptr;            // host view; [0] published, [16] stop word, [32] exit word
-        DevJob* jobs = nullptr;
-        uint64_t* tstart = nullptr;
+        uint64_t* hdr = nullptr;            // host view; [16] stop word, [32] exit word
+        uint64_t* words = nullptr;          // kRing slots of kRingWords tagged words
         uint64_t* flags = nullptr;
-        void *hdr_d = nullptr, *jobs_d = nullptr, *tstart_d = nullptr, *flags_d = nullptr;
+        void *hdr_d = nullptr, *words_d = nullptr, *flags_d = nullptr;
         char* ws = nullptr;
         ResLayout L{};
         int grid = 0;
@@ -1120,7 +1174,7 @@ struct hipmr_server {
         void* tpart = w + res.L.tpart;
         unsigned long long mask = res.L.tp - 1, jb = res.next_seq, tb = res.next_tile, ep = res.epoch,
                            dl = res.deadline_ticks;
-        void* a[17] = {&res.hdr_d, &res.jobs_d, &res.tstart_d, &res.flags_d, &ctrl, &dring, &dtstart,
+        void* a[15] = {&res.hdr_d, &res.words_d, &res.flags_d, &ctrl, &dring, &dtstart,
                        &gdone, &jdone, &gpart, &tpart, &mask, &jb, &tb, &ep, &dl};
         if (e == hipSuccess)
             e = hipModuleLaunchKernel(f_res, (unsigned)res.grid, 1, 1, 1024, 1, 1, 0, res.stream, a, nullptr);
@@ -1197,11 +1251,22 @@ struct hipmr_server {
                     continue;
                 }
             }
+            // the nine tagged words of the job's slot (their order does not
+            // matter: the device takes the slot once all nine carry the tag)
             const uint64_t slot = res.next_seq & (kRing - 1);
-            res.jobs[slot] = DevJob{p.job.x, p.job.y, p.job.w, p.job.n, p.job.tmpl, p.job.dtype, 0, p.head,
-                                    p.job.out, p.job.a, p.job.b};
-            res.tstart[slot] = res.next_tile;
-            __atomic_store_n(&res.hdr[0], res.next_seq + 1, __ATOMIC_RELEASE);
+            const uint64_t tag = ((res.next_seq / kRing + 1) & 0xffff) << 48;
+            uint32_t ab[2];
+            std::memcpy(&ab[0], &p.job.a, 4);
+            std::memcpy(&ab[1], &p.job.b, 4);
+            const uint64_t f[9] = {(uint64_t)(uintptr_t)p.job.x, (uint64_t)(uintptr_t)p.job.y,
+                                   (uint64_t)(uintptr_t)p.job.w, (uint64_t)p.job.n,
+                                   (uint64_t)(uintptr_t)p.job.out,
+                                   (uint64_t)p.job.tmpl | ((uint64_t)p.job.dtype << 8) |
+                                       ((uint64_t)(uint16_t)(int16_t)p.head << 16) |   // head: -1 or 0..7
+                                       ((res.epoch & 0xffff) << 32),                    // the instance's
+                                   ab[0], ab[1], res.next_tile};
+            uint64_t* dst = res.words + slot * kRingWords;
+            for (int k = 0; k < 9; ++k) __atomic_store_n(dst + k, tag | (f[k] & kField), __ATOMIC_RELEASE);
             res.flights.push_back({p, res.next_seq, res.next_tile, tiles, now_ns(),
                                    (int32_t)res.flights.size() + 1});
             admitted += p.bytes;
@@ -1435,6 +1500,10 @@ hipmr_status validate_job(const hipmr_server* s, const hipmr_sjob* j) {
                                          "2^27 bfloat16 elements)");
     if (job_tiles(*j, job_head(*j)) > s->cfg.max_batch_tiles)
         return fail(HIPMR_E_BUDGET, "the job has more tiles than max_batch_tiles");
+    if (s->cfg.resident &&
+        (((uintptr_t)j->x | (uintptr_t)j->y | (uintptr_t)j->w | (uintptr_t)j->out) > kField ||
+         (uint64_t)j->n > kField))
+        return fail(HIPMR_E_UNSUPPORTED, "the resident ring carries addresses and lengths below 2^48");
     return HIPMR_OK;
 }
 
@@ -1498,22 +1567,20 @@ hipmr_status hipmr_server_create(const hipmr_server_config* in, void* workspace,
             khz < 1000 || khz > 10000000)
             return fail(HIPMR_E_HIP, "the device wall clock rate is unknown");
         r.deadline_ticks = (uint64_t)(kLifeS * 1e3 * khz);
-        const size_t ring = 512 + (size_t)kRing * (sizeof(DevJob) + 16);
+        const size_t ring = 512 + (size_t)kRing * (kRingWords * 8 + 8);
         // default-priority, non-blocking stream; the ring in mapped, coherent host memory
         if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess ||
             hipHostMalloc((void**)&r.hdr, ring, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
             return fail(HIPMR_E_HIP, "creating the resident stream or its host ring failed");
         std::memset(r.hdr, 0, ring);
-        r.jobs = (DevJob*)((char*)r.hdr + 512);
-        r.tstart = (uint64_t*)(r.jobs + kRing);
-        r.flags = r.tstart + kRing;
+        r.words = (uint64_t*)((char*)r.hdr + 512);
+        r.flags = r.words + (size_t)kRing * kRingWords;
         void* hd = nullptr;
         if (hipHostGetDevicePointer(&hd, r.hdr, 0) != hipSuccess)
             return fail(HIPMR_E_HIP, "hipHostGetDevicePointer failed for the host ring");
         r.hdr_d = hd;
-        r.jobs_d = (char*)hd + 512;
-        r.tstart_d = (char*)r.jobs_d + (size_t)kRing * sizeof(DevJob);
-        r.flags_d = (char*)r.tstart_d + (size_t)kRing * 8;
+        r.words_d = (char*)hd + 512;
+        r.flags_d = (char*)r.words_d + (size_t)kRing * kRingWords * 8;
         // no instance yet: the stop word names epoch 0, which never runs
         r.hdr[16] = 0;
         if (hipMemsetAsync(workspace, 0, r.L.total, r.stream) != hipSuccess ||
