@@ -4,7 +4,8 @@ path (no instance, a stopped instance, an instance that stops when idle),
 every job against the oracle, results bitwise equal to the launched paths
 (batched and one launch pair per job) and to the same job alone, instances
 replaced while a stream runs, empty / one-element / misaligned jobs, budget
-admission, and the full-size stream."""
+admission, the full-size stream, the ring's 48-bit fields and a burst of jobs
+due at once."""
 
 import math
 import time
@@ -200,3 +201,35 @@ def test_resident_full_size_stream(dev):
         oracle_check(int(k), float(got[k]), sched, full)
     del full
     torch.cuda.empty_cache()
+
+
+def test_resident_ring_refuses_fields_past_48_bits(dev, pool):
+    # the resident ring carries addresses and lengths as 48-bit fields: a job
+    # beyond them is refused at submission (nothing reaches the device), and
+    # the server goes on serving
+    sched = workloads.serving_schedule(10000, 0.003, pool_n=POOL_N, log2_max=12)
+    out = torch.full((len(sched["n"]),), float("nan"), dtype=torch.float64, device=dev)
+    server = hm.Server(resident=1)
+    jobs = make_jobs(server, sched, pool, out)
+    for field in ("x", "out"):
+        bad = jobs[0].copy()
+        bad[field] = np.uint64(1 << 48)
+        with pytest.raises(hm.UnsupportedError):
+            server.submit(bad)
+    server.submit(jobs[0].copy())
+    server.wait_idle()
+    server.close()
+    torch.cuda.synchronize()
+    oracle_check(0, float(out.cpu().numpy()[0]), sched, pool)
+
+
+def test_resident_burst_of_jobs_at_once(dev, pool):
+    # 300 jobs due at the same instant: the dispatcher takes up to seven
+    # complete ring slots per read; every result equals the launched path's
+    sched = workloads.serving_schedule(10000, 0.04, pool_n=POOL_N, log2_max=14)
+    sched["arrival_ns"][:] = 0
+    assert len(sched["n"]) >= 300
+    got, done = run(sched, pool, dev, resident=1)
+    ref, _ = run(sched, pool, dev, nstreams=4)
+    assert np.all(done["status"] == 0)
+    assert same_bits(got, ref)
