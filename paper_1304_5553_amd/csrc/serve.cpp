@@ -292,17 +292,21 @@ __device__ __forceinline__ double2 hipmr_fin_groups(bool mx, const double2* gv, 
 // only once it is visible to the whole system, so waiting for it (rather
 // than a system-scope fence, which writes back the whole L2) orders it
 // before the flag.
-__device__ __forceinline__ void hipmr_job_post(const hipmr_sjob& J, double2 tot,
-                                               unsigned long long* flag, unsigned long long seq) {
+__device__ __forceinline__ void hipmr_job_post_to(int tmpl, double* out, double2 tot,
+                                                  unsigned long long* flag, unsigned long long seq) {
   double r = tot.x;
-  if (J.tmpl == 2) r = sqrt(r);
-  else if (J.tmpl == 7) r = r / tot.y;
-  __hip_atomic_store((unsigned long long*)J.out, __builtin_bit_cast(unsigned long long, r), __ATOMIC_RELAXED,
+  if (tmpl == 2) r = sqrt(r);
+  else if (tmpl == 7) r = r / tot.y;
+  __hip_atomic_store((unsigned long long*)out, __builtin_bit_cast(unsigned long long, r), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_SYSTEM);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __hip_atomic_store(flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void hipmr_job_post(const hipmr_sjob& J, double2 tot,
+                                               unsigned long long* flag, unsigned long long seq) {
+  hipmr_job_post_to(J.tmpl, J.out, tot, flag, seq);
 }
 
 // The fold of the partials [t0, t1) by one block of 1024 threads: wave w
@@ -645,7 +649,9 @@ extern "C" __global__ void __launch_bounds__(1024)
   __shared__ unsigned long long sh_js[16];     // that job's first tile
   __shared__ int sh_k[16];                     // its tile index in the job (-1: none)
   __shared__ float2 sh_part[16];               // the tile's partial
-  __shared__ hipmr_sjob sh_job[16];            // that job's descriptor
+  __shared__ int sh_nt[16];                    // the wave's current job: its tiles,
+  __shared__ int sh_tm[16];                    // template
+  __shared__ unsigned long long sh_out[16];    // and result address
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
   const unsigned long long start = wall_clock64();
@@ -719,6 +725,13 @@ extern "C" __global__ void __launch_bounds__(1024)
           cjs = hipmr_ld_agent(dtstart + slot);
           cJ = hipmr_job_ld(dring + slot, false);
           cnt = hipmr_job_ntiles(cJ);
+          // for the group fold: the wave's current job, as long as the wave
+          // keeps it (written only here, read after the barrier)
+          if (lane == 0) {
+            sh_nt[w] = cnt;
+            sh_tm[w] = cJ.tmpl;
+            sh_out[w] = (unsigned long long)cJ.out;
+          }
         }
         myk = (int)(G - cjs);
         r = hipmr_job_dispatch(cJ, myk, lane);
@@ -729,7 +742,6 @@ extern "C" __global__ void __launch_bounds__(1024)
         sh_js[w] = cjs;
         sh_k[w] = myk;
         sh_part[w] = r;
-        if (myk >= 0) sh_job[w] = cJ;
       }
       hipmr_drain();                        // this wave's partial is written
       __syncthreads();
@@ -753,12 +765,9 @@ extern "C" __global__ void __launch_bounds__(1024)
           }
         }
         bool full = false, local = false;
-        unsigned long long jw[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // the head lane's job descriptor
         if (head) {
           const unsigned long long slot = s & (HIPMR_RING - 1);
-          const hipmr_sjob Jh = sh_job[lane];     // the job's descriptor, as the wave read it
-          __builtin_memcpy(jw, &Jh, sizeof(Jh));
-          const int ntiles_h = hipmr_job_ntiles(Jh);
+          const int ntiles_h = sh_nt[lane];       // the job's tiles, as the wave read them
           const int gsize = ntiles_h - 64 * g < 64 ? ntiles_h - 64 * g : 64;
           if (run == gsize) {
             // the whole group is in this round: no other block holds any of its tiles
@@ -779,15 +788,10 @@ extern "C" __global__ void __launch_bounds__(1024)
           const unsigned long long fs = __shfl(s, hl, 64);
           const int fg = __shfl(g, hl, 64);
           const bool flocal = __shfl((int)local, hl, 64) != 0;
-          unsigned long long fw[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) fw[q] = __shfl(jw[q], hl, 64);
-          hipmr_sjob J;
-          __builtin_memcpy(&J, fw, sizeof(J));
           const unsigned long long slot = fs & (HIPMR_RING - 1);
           const unsigned long long js = sh_js[hl];
-          const int ntiles = hipmr_job_ntiles(J), ng = (ntiles + 63) / 64;
-          const bool mx = J.tmpl == 3;
+          const int ntiles = sh_nt[hl], ng = (ntiles + 63) / 64, tmpl = sh_tm[hl];
+          const bool mx = tmpl == 3;
           double2 gv;
           if (flocal) {                     // the group's partials are this block's: from LDS
             const int gsize = ntiles - 64 * fg < 64 ? ntiles - 64 * fg : 64;
@@ -835,7 +839,7 @@ extern "C" __global__ void __launch_bounds__(1024)
             }
           }
           if (last && lane == 0) {
-            hipmr_job_post(J, tot, hr_flags + slot, fs + 1);
+            hipmr_job_post_to(tmpl, (double*)sh_out[hl], tot, hr_flags + slot, fs + 1);
             __hip_atomic_fetch_add(ctrl + 16, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
