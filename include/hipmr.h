@@ -431,8 +431,8 @@ typedef struct hipmr_server_config {
     int32_t nstreams;            /* batches in flight, one stream each (1..16); 0: 4                */
     int32_t max_batch_jobs;      /* jobs per batch (1..4096; 1 = one launch pair per job); 0: 1024  */
     int32_t max_batch_tiles;     /* tiles per batch (a tile is 1024 float32 / 2048 bfloat16
-                                    elements, 2-8 times that in jobs of over 2^23 / 2^24
-                                    elements, so that no job has more than 8192); 0: 2^18         */
+                                    elements, P times that, P = ceil(those tiles / 4080), in
+                                    jobs that would have more than 4080); 0: 2^18               */
     int32_t blocks_per_cu;       /* persistent grid of the tile kernel; 0: 8                        */
     uint64_t max_batch_bytes;    /* input bytes per batch of two or more jobs; 0: 16 MiB           */
     uint64_t solo_bytes;         /* a job of more input bytes runs in a batch of its own, and
@@ -496,8 +496,8 @@ size_t hipmr_server_workspace_bytes(const hipmr_server_config *cfg);
  * On every path a job's tiles depend only on the job, and its tile partials
  * are folded in a fixed order (64-tile groups, then the groups), so its
  * result is bitwise the same alone, in any mix and on any path.  A job has at
- * most 8192 tiles (2^26 float32 / 2^27 bfloat16 elements; E_UNSUPPORTED
- * beyond).
+ * most 4080 tiles (the resident kernel takes them in one round) and at most
+ * 2^26 float32 / 2^27 bfloat16 elements (E_UNSUPPORTED beyond).
  * Completion is observed through per-job flags in mapped host memory that the
  * folding wave or block writes after the result (a stream query is the
  * watchdog for errors).  Inputs stay resident: jobs name device arrays.  The

@@ -23,7 +23,7 @@
 //     written by the finishing block after the result (querying the stream
 //     serves as a watchdog for errors).
 // A job's tiles depend only on the job (its length, dtype and alignment; big
-// jobs get longer tiles so that none has more than 8192), so its result is
+// jobs get longer tiles so that none has more than 4080), so its result is
 // bitwise the same alone or in any mix.  A batch of one job passes its
 // descriptor by value; with max_batch_jobs = 1 every job runs that way, one
 // launch pair per job: the baseline.
@@ -52,7 +52,9 @@ constexpr int kInlineJobs = 24;          // descriptors passed as kernel argumen
 constexpr int kMaxSkipped = 64;          // large jobs one batch of small ones may be packed past
 constexpr int kOneLaunchTiles = 16;      // a job of at most this many tiles alone: one launch
 constexpr int64_t kWatchdogNs = 20000000;  // after 20 ms without flags, query the stream
-constexpr int kMaxJobTiles = 8192;       // tiles of one job (its fold has at most 128 groups)
+constexpr int kRoundTiles = 4080;        // tiles of one job at most: a round of the resident kernel
+                                         // (255 worker CUs x 16 waves, one tile each)
+constexpr long long kMaxBaseTiles = 65536;  // one-pass tiles of the largest job (2^26 f32, 2^27 bf16)
 constexpr int kRing = 4096;               // resident: job descriptors in flight (power of two)
 constexpr int kRingWords = 16;            // resident: 64-bit words per host ring slot (nine used)
 constexpr uint64_t kField = (1ull << 48) - 1;   // resident: a ring word's payload
@@ -118,21 +120,23 @@ __device__ __forceinline__ float2 hipmr_job_comb2(float2 a, float2 b) {
 // Tile geometry of a job, a function of the job alone: `ab` unaligned head
 // elements (all arrays 16-byte aligned after them; 0 when they share no
 // alignment), then tiles of `tt` elements = P passes of 64 lanes x 4 chunks x
-// V elements.  P (1, 2, 4 or 8) is the smallest that keeps the job at or
-// under 8192 tiles (jobs that need more are refused when submitted); arrays
-// without a common alignment take their tiles element by element.
+// V elements.  P is the smallest that keeps the job at or under 4080 tiles,
+// which the resident kernel's 4080 waves take in one round (1 up to 2^22
+// float32 elements, 17 at 2^26, the largest job taken); arrays without a
+// common alignment take their tiles element by element.
 struct hipmr_geom { long long ab, tt; int passes, tiles; };
 
 __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
-  const long long tt0 = J.dtype == @@BF16CODE@@ ? 64 * 8 * 4 : 64 * 4 * 4;
+  const int lg = J.dtype == @@BF16CODE@@ ? 11 : 10;      // one-pass tile: 2^lg elements
   hipmr_geom g;
   g.ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
   const long long body = J.n - g.ab;
-  int p = 1;
-  while (p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
+  const long long t1 = (body + (1ll << lg) - 1) >> lg;
+  const int p = t1 > @@ROUND_TILES@@ ? (int)((t1 + @@ROUND_TILES@@ - 1) / @@ROUND_TILES@@) : 1;
   g.passes = p;
-  g.tt = tt0 * p;
-  const long long t = (body + g.tt - 1) / g.tt;
+  g.tt = (long long)p << lg;
+  // ceil(body / (p 2^lg)) = ceil(t1 / p); t1 <= 2^16 for every job admitted
+  const long long t = p == 1 ? t1 : (long long)(((unsigned)t1 + (unsigned)p - 1) / (unsigned)p);
   g.tiles = J.n <= 0 ? 0 : (t < 1 ? 1 : (int)t);
   return g;
 }
@@ -141,7 +145,7 @@ __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
 // head.  Lane l takes chunks l + 64 (u + 4 p) of the tile; each chunk's V
 // terms are summed pairwise, then added to accumulator u (one per chunk
 // slot, across the P passes); the 4 accumulators fold pairwise, then across
-// the wave.  Every float sum on the way has depth <= 19.
+// the wave.  Every float sum on the way has depth <= P + 11 (28 at most).
 template <int TMPL, typename T, int V>
 __device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long k, int lane) {
   constexpr int U = 4;
@@ -239,7 +243,8 @@ __device__ __forceinline__ float2 hipmr_job_dispatch(const hipmr_sjob& J, long l
 // result never depends on the path that ran it.  FP64, in two levels:
 //   1. group g of 64 consecutive tiles: lane l holds partial 64 g + l (the
 //      neutral element past the job's last tile), then the wave butterfly;
-//   2. the groups (at most 128, as a job has at most 8192 tiles): lane l
+//   2. the groups (at most 64, as a job has at most 4080 tiles; room for
+//      128): lane l
 //      folds the neutral element, group l and group l + 64 in that order,
 //      then the wave butterfly.
 // Every lane ends with the same value.  The second component (the weight of
@@ -884,8 +889,8 @@ int job_tiles(const hipmr_sjob& j, int head) {
     const long long tt0 = tile_elems(j.dtype);
     const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
     const long long body = j.n - ab;
-    long long p = 1;
-    while (p < 8 && (body + tt0 * p - 1) / (tt0 * p) > 8192) p *= 2;
+    const long long t1 = (body + tt0 - 1) / tt0;
+    const long long p = t1 > kRoundTiles ? (t1 + kRoundTiles - 1) / kRoundTiles : 1;
     const long long t = (body + tt0 * p - 1) / (tt0 * p);
     return (int)std::max<long long>(t, 1);
 }
@@ -963,6 +968,7 @@ std::string serve_source(const std::string& prefix) {
     };
     rep("@@PREFIX@@", prefix);
     rep("@@BF16CODE@@", std::to_string(HIPMR_BF16));
+    rep("@@ROUND_TILES@@", std::to_string(kRoundTiles));
     rep("@@NINLINE@@", std::to_string(kInlineJobs));
     rep("@@RING@@", std::to_string(kRing));
     rep("@@RING_WORDS@@", std::to_string(kRingWords));
@@ -1499,9 +1505,8 @@ hipmr_status validate_job(const hipmr_server* s, const hipmr_sjob* j) {
         return fail(HIPMR_E_INVALID, "an input array of the job's template is NULL");
     if (job_bytes(*j) > s->cfg.hbm_budget_bytes)
         return fail(HIPMR_E_BUDGET, "the job alone exceeds the memory budget");
-    if (job_tiles(*j, job_head(*j)) > kMaxJobTiles)
-        return fail(HIPMR_E_UNSUPPORTED, "the job has more than 8192 tiles (over 2^26 float32 or "
-                                         "2^27 bfloat16 elements)");
+    if ((std::max<int64_t>(j->n, 0) + tile_elems(j->dtype) - 1) / tile_elems(j->dtype) > kMaxBaseTiles)
+        return fail(HIPMR_E_UNSUPPORTED, "the job is over 2^26 float32 or 2^27 bfloat16 elements");
     if (job_tiles(*j, job_head(*j)) > s->cfg.max_batch_tiles)
         return fail(HIPMR_E_BUDGET, "the job has more tiles than max_batch_tiles");
     if (s->cfg.resident &&

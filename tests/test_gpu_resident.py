@@ -4,8 +4,8 @@ path (no instance, a stopped instance, an instance that stops when idle),
 every job against the oracle, results bitwise equal to the launched paths
 (batched and one launch pair per job) and to the same job alone, instances
 replaced while a stream runs, empty / one-element / misaligned jobs, budget
-admission, the full-size stream, the ring's 48-bit fields and a burst of jobs
-due at once."""
+admission, the full-size stream, the ring's 48-bit fields, a burst of jobs
+due at once and the largest jobs taken."""
 
 import math
 import time
@@ -233,3 +233,41 @@ def test_resident_burst_of_jobs_at_once(dev, pool):
     ref, _ = run(sched, pool, dev, nstreams=4)
     assert np.all(done["status"] == 0)
     assert same_bits(got, ref)
+
+
+def test_resident_largest_jobs_and_one_past(dev):
+    # the largest jobs taken (2^26 float32 elements: 17 passes per tile, 3856
+    # tiles), ragged and misaligned ones beside them, float32 and bfloat16, on
+    # the resident kernel and on one launch pair per job, bit for bit; one
+    # element past the limit is refused at submission
+    big = 1 << 26
+    f32, bf16 = workloads.serving_pool(big + 8)
+    full = (f32, bf16, {k: torch.from_numpy(v).to(dev) for k, v in f32.items()},
+            {k: torch.from_numpy(v.view(np.int16)).view(torch.bfloat16).to(dev) for k, v in bf16.items()})
+    sched = {"n": np.array([big, big - 3, big - 1000, big, big - 5, big, big - 77, big], np.int64),
+             "tmpl": np.array([0, 1, 3, 7, 2, 6, 4, 5], np.int32),
+             "bf16": np.array([0, 0, 0, 0, 1, 1, 1, 1], bool),
+             "offset": np.array([0, 1, 3, 0, 2, 0, 5, 0], np.int64),
+             "arrival_ns": np.arange(8, dtype=np.int64) * 2_000_000}
+    got, done = run(sched, full, dev, resident=1, hbm_budget_bytes=64 << 30)
+    ref, _ = run(sched, full, dev, hbm_budget_bytes=64 << 30, nstreams=1, max_batch_jobs=1)
+    assert np.all(done["status"] == 0) and same_bits(got, ref)
+    # the oracle takes 10-20 s per job this long: the float32 sum and the
+    # ragged, misaligned dot; the max and the count are exact
+    for k in (0, 1):
+        oracle_check(k, float(got[k]), sched, full)
+    assert got[2] == float(np.max(f32["x"][3:3 + big - 1000]))
+    xb = torch.from_numpy(bf16["x"][:big].view(np.int16)).view(torch.bfloat16).float()
+    assert got[7] == float(torch.count_nonzero(xb > 0))
+    for mode, kw in (("resident", dict(resident=1)), ("per_job", dict(nstreams=1, max_batch_jobs=1))):
+        out = torch.zeros(2, dtype=torch.float64, device=dev)
+        server = hm.Server(hbm_budget_bytes=64 << 30, **kw)
+        jobs = make_jobs(server, {k: v[:2] for k, v in sched.items()}, full, out)
+        jobs["n"] = [big + 1, 2 * big + 1]
+        jobs["dtype"] = [hm.hipmr.F32, hm.hipmr.BF16]
+        for k in range(2):
+            with pytest.raises(hm.UnsupportedError):
+                server.submit(jobs[k].copy())
+        server.close()
+    del full
+    torch.cuda.empty_cache()
