@@ -119,24 +119,26 @@ __device__ __forceinline__ float2 hipmr_job_comb2(float2 a, float2 b) {
 
 // Tile geometry of a job, a function of the job alone: `ab` unaligned head
 // elements (all arrays 16-byte aligned after them; 0 when they share no
-// alignment), then tiles of `tt` elements = P passes of 64 lanes x 4 chunks x
-// V elements.  P is the smallest that keeps the job at or under 4080 tiles,
-// which the resident kernel's 4080 waves take in one round (1 up to 2^22
-// float32 elements, 17 at 2^26, the largest job taken); arrays without a
-// common alignment take their tiles element by element.
+// alignment), then tiles of `tt` elements = Q chunks of V elements per lane
+// x 64 lanes, taken in P = ceil(Q / 4) passes of up to 4 chunks per lane.
+// Q is 4 while that keeps the job at or under 4080 tiles (up to 2^22 float32
+// / 2^23 bfloat16 elements), else the smallest that does (17 at 2^24 float32
+// elements, 65 at 2^26, the largest job taken): the resident kernel's 4080
+// waves take every job in one round.  Arrays without a common alignment take
+// their tiles element by element.
 struct hipmr_geom { long long ab, tt; int passes, tiles; };
 
 __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
-  const int lg = J.dtype == @@BF16CODE@@ ? 11 : 10;      // one-pass tile: 2^lg elements
+  const int lg = J.dtype == @@BF16CODE@@ ? 9 : 8;        // one chunk per lane: 2^lg elements
   hipmr_geom g;
   g.ab = J.head >= 0 ? (J.head < J.n ? J.head : J.n) : 0;
   const long long body = J.n - g.ab;
-  const long long t1 = (body + (1ll << lg) - 1) >> lg;
-  const int p = t1 > @@ROUND_TILES@@ ? (int)((t1 + @@ROUND_TILES@@ - 1) / @@ROUND_TILES@@) : 1;
-  g.passes = p;
-  g.tt = (long long)p << lg;
-  // ceil(body / (p 2^lg)) = ceil(t1 / p); t1 <= 2^16 for every job admitted
-  const long long t = p == 1 ? t1 : (long long)(((unsigned)t1 + (unsigned)p - 1) / (unsigned)p);
+  const long long c1 = (body + (1ll << lg) - 1) >> lg;
+  const int q = c1 > 4 * @@ROUND_TILES@@ ? (int)((c1 + @@ROUND_TILES@@ - 1) / @@ROUND_TILES@@) : 4;
+  g.passes = (q + 3) / 4;
+  g.tt = (long long)q << lg;
+  // ceil(body / (q 2^lg)) = ceil(c1 / q); c1 <= 2^18 for every job admitted
+  const long long t = q == 4 ? (c1 + 3) >> 2 : (long long)(((unsigned)c1 + (unsigned)q - 1) / (unsigned)q);
   g.tiles = J.n <= 0 ? 0 : (t < 1 ? 1 : (int)t);
   return g;
 }
@@ -146,6 +148,7 @@ __device__ __forceinline__ hipmr_geom hipmr_job_geom(const hipmr_sjob& J) {
 // terms are summed pairwise, then added to accumulator u (one per chunk
 // slot, across the P passes); the 4 accumulators fold pairwise, then across
 // the wave.  Every float sum on the way has depth <= P + 11 (28 at most).
+// The last pass may hold fewer than 4 chunks per lane.
 template <int TMPL, typename T, int V>
 __device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long k, int lane) {
   constexpr int U = 4;
@@ -315,7 +318,8 @@ __device__ __forceinline__ void hipmr_job_post(const hipmr_sjob& J, double2 tot,
 }
 
 // The fold of the partials [t0, t1) by one block of 1024 threads: wave w
-// takes groups w, w + 16, ...; wave 0 then folds the groups and finishes.
+// takes groups w, w + 16, ... (the loads of up to four issued together);
+// wave 0 then folds the groups and finishes.
 constexpr int HIPMR_FIN_BLOCK = 1024;
 
 __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, int t1,
@@ -325,9 +329,25 @@ __device__ __forceinline__ void hipmr_job_finish(const hipmr_sjob& J, int t0, in
   const bool mx = J.tmpl == 3;
   const int ntiles = t1 - t0, ng = (ntiles + 63) / 64;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int g = w; g < ng; g += HIPMR_FIN_BLOCK / 64) {
-    const double2 v = hipmr_fin_group(mx, tpart, (unsigned long long)t0, ~0ull, g, ntiles, lane);
-    if (lane == 0) hipmr_gv[g] = v;
+  constexpr int S = HIPMR_FIN_BLOCK / 64;
+  for (int g0 = w; g0 < ng; g0 += 4 * S) {
+    // unconditional loads (the index clamped into [t0, t1)), so that no
+    // branch separates them and all four are in flight together
+    float2 p[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 64 * (g0 + S * i) + lane;
+      p[i] = tpart[t0 + (k < ntiles ? k : ntiles - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int g = g0 + S * i, k = 64 * g + lane;
+      if (g < ng) {                       // the fold of hipmr_fin_group
+        const double2 v = hipmr_fin_wave(mx, k < ntiles ? make_double2((double)p[i].x, (double)p[i].y)
+                                                        : hipmr_fin_neutral(mx));
+        if (lane == 0) hipmr_gv[g] = v;
+      }
+    }
   }
   __syncthreads();
   if (w == 0) {
@@ -889,9 +909,10 @@ int job_tiles(const hipmr_sjob& j, int head) {
     const long long tt0 = tile_elems(j.dtype);
     const long long ab = head >= 0 ? std::min<long long>(head, j.n) : 0;
     const long long body = j.n - ab;
-    const long long t1 = (body + tt0 - 1) / tt0;
-    const long long p = t1 > kRoundTiles ? (t1 + kRoundTiles - 1) / kRoundTiles : 1;
-    const long long t = (body + tt0 * p - 1) / (tt0 * p);
+    const long long ch = tt0 / 4;                 // one chunk per lane
+    const long long c1 = (body + ch - 1) / ch;
+    const long long q = c1 > 4 * kRoundTiles ? (c1 + kRoundTiles - 1) / kRoundTiles : 4;
+    const long long t = (body + ch * q - 1) / (ch * q);
     return (int)std::max<long long>(t, 1);
 }
 

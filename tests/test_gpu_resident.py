@@ -236,7 +236,7 @@ def test_resident_burst_of_jobs_at_once(dev, pool):
 
 
 def test_resident_largest_jobs_and_one_past(dev):
-    # the largest jobs taken (2^26 float32 elements: 17 passes per tile, 3856
+    # the largest jobs taken (2^26 float32 elements: 17 passes per tile, 4033
     # tiles), ragged and misaligned ones beside them, float32 and bfloat16, on
     # the resident kernel and on one launch pair per job, bit for bit; one
     # element past the limit is refused at submission
