@@ -503,6 +503,11 @@ extern "C" __global__ void __launch_bounds__(1024)
 // invalidate the whole L2 at every tile.)
 #define HIPMR_RING @@RING@@
 
+__device__ __forceinline__ unsigned long long hipmr_readlane64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return (unsigned long long)hi << 32 | lo;
+}
 __device__ __forceinline__ unsigned long long hipmr_ld_agent(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -526,6 +531,9 @@ __device__ __forceinline__ hipmr_sjob hipmr_job_ld(const hipmr_sjob* p, bool sys
   unsigned long long v[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = system ? hipmr_ld_sys(w + k) : hipmr_ld_agent(w + k);
+  // every lane read the same words: keep them in scalar registers
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = hipmr_readlane64(v[k], 0);
   hipmr_sjob J;
   __builtin_memcpy(&J, v, sizeof(J));
   return J;
@@ -677,7 +685,8 @@ extern "C" __global__ void __launch_bounds__(1024)
   __shared__ int sh_nt[16];                    // the wave's current job: its tiles,
   __shared__ int sh_tm[16];                    // template
   __shared__ unsigned long long sh_out[16];    // and result address
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform: a scalar register, not a vector one per lane
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   unsigned long long* rep = ctrl + 32 + 16 * (blockIdx.x & 7);
   const unsigned long long start = wall_clock64();
   // the wave's current job (its tiles are mostly consecutive tickets)
@@ -712,6 +721,7 @@ extern "C" __global__ void __launch_bounds__(1024)
       const unsigned long long avail = pub < t0 + 16 ? pub : t0 + 16;
       const unsigned long long T = t0 + w;
       int myk = -1;
+      bool stored = false;
       float2 r = make_float2(0.0f, 0.0f);
       if (T >= done && T < avail) {
         const unsigned long long G = tile_base + T, fresh = tile_base + pub;
@@ -722,6 +732,13 @@ extern "C" __global__ void __launch_bounds__(1024)
           unsigned long long lo = hint;
           if (njobs > HIPMR_RING && njobs - HIPMR_RING > lo) lo = njobs - HIPMR_RING;
           unsigned long long hi = njobs - 1;
+          // the newest job's descriptor (lanes 0..7, a word each) and first
+          // tile (lane 8), read alongside the search: under light load the
+          // tile is usually the newest job's, which then costs no second trip
+          const unsigned long long hi0 = hi, sslot = hi0 & (HIPMR_RING - 1);
+          unsigned long long spec = 0;
+          if (lane < 9)
+            spec = hipmr_ld_agent(lane < 8 ? (const unsigned long long*)(dring + sslot) + lane : dtstart + sslot);
           while (lo < hi) {
             // lane 63 checks the newest job first: under light load the tile is usually its
             const unsigned long long step = (hi - lo + 64) / 64;
@@ -746,9 +763,17 @@ extern "C" __global__ void __launch_bounds__(1024)
           }
           hint = lo;
           cs = lo;
-          const unsigned long long slot = lo & (HIPMR_RING - 1);
-          cjs = hipmr_ld_agent(dtstart + slot);
-          cJ = hipmr_job_ld(dring + slot, false);
+          if (lo == hi0) {
+            unsigned long long v[8];
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) v[k2] = hipmr_readlane64(spec, k2);
+            __builtin_memcpy(&cJ, v, sizeof(cJ));
+            cjs = hipmr_readlane64(spec, 8);
+          } else {
+            const unsigned long long slot = lo & (HIPMR_RING - 1);
+            cjs = hipmr_ld_agent(dtstart + slot);
+            cJ = hipmr_job_ld(dring + slot, false);
+          }
           cnt = hipmr_job_ntiles(cJ);
           // for the group fold: the wave's current job, as long as the wave
           // keeps it (written only here, read after the barrier)
@@ -760,7 +785,15 @@ extern "C" __global__ void __launch_bounds__(1024)
         }
         myk = (int)(G - cjs);
         r = hipmr_job_dispatch(cJ, myk, lane);
-        if (lane == 0) hipmr_st_agent(tpart + (G & tp_mask), __builtin_bit_cast(unsigned long long, r));
+        // a group whose tiles all fall in this round ([done, avail), the
+        // test the group count below makes) is folded from LDS: only the
+        // partials of other groups go to global memory
+        const int g0 = myk & ~63;
+        const unsigned long long gs = cjs + (unsigned long long)g0 - tile_base;
+        const int gsz = cnt - g0 < 64 ? cnt - g0 : 64;
+        stored = !(gs >= done && gs + (unsigned long long)gsz <= avail);
+        if (stored && lane == 0)
+          hipmr_st_agent(tpart + (G & tp_mask), __builtin_bit_cast(unsigned long long, r));
       }
       if (lane == 0) {
         sh_seq[w] = cs;
@@ -768,7 +801,7 @@ extern "C" __global__ void __launch_bounds__(1024)
         sh_k[w] = myk;
         sh_part[w] = r;
       }
-      hipmr_drain();                        // this wave's partial is written
+      if (stored) hipmr_drain();            // this wave's partial is written
       __syncthreads();
       if (w == 0) {
         // count the round's tiles into their groups: lane l < 16 stands for
