@@ -94,6 +94,48 @@ struct hipmr_sjob {
   float a, b;
 };
 
+// Lane moves (every lane of the wave active): DPP inside rows of 16 lanes,
+// v_readlane for one lane's value.
+template <int CTRL>
+__device__ __forceinline__ unsigned hipmr_dpp32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float hipmr_dpp(float v) {
+  return __builtin_bit_cast(float, hipmr_dpp32<CTRL>(__builtin_bit_cast(unsigned, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double hipmr_dpp(double v) {
+  const unsigned long long a = __builtin_bit_cast(unsigned long long, v);
+  return __builtin_bit_cast(double, (unsigned long long)hipmr_dpp32<CTRL>((unsigned)(a >> 32)) << 32 |
+                                        hipmr_dpp32<CTRL>((unsigned)a));
+}
+__device__ __forceinline__ unsigned long long hipmr_readlane64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return (unsigned long long)hi << 32 | lo;
+}
+__device__ __forceinline__ float hipmr_rl(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double hipmr_rl(double v, int l) {
+  return __builtin_bit_cast(double, hipmr_readlane64(__builtin_bit_cast(unsigned long long, v), l));
+}
+
+// Butterfly fold of a commutative op over the wave, lane distance 1, 2, 4, 8
+// (DPP quad permutations, then the half-row and row mirrors: once each quad,
+// then each half-row, holds one value, the mirror partner is as good as the
+// xor partner), then 16 and 32 (one lane read from each row).  Every lane
+// ends with the same value; the tree has depth 6.
+template <typename T, typename Op>
+__device__ __forceinline__ T hipmr_wave_fold(T v, Op op) {
+  v = op(v, hipmr_dpp<0xb1>(v));         // lane ^ 1
+  v = op(v, hipmr_dpp<0x4e>(v));         // lane ^ 2
+  v = op(v, hipmr_dpp<0x141>(v));        // the other quad of the half-row
+  v = op(v, hipmr_dpp<0x140>(v));        // the other half of the row
+  return op(op(hipmr_rl(v, 0), hipmr_rl(v, 16)), op(hipmr_rl(v, 32), hipmr_rl(v, 48)));
+}
+
 // One element's terms (t0, t1) under template TMPL; t1 is the weight of the
 // weighted mean and 0 otherwise.
 template <int TMPL>
@@ -213,9 +255,8 @@ __device__ __forceinline__ float2 hipmr_job_tile(const hipmr_sjob& J, long long 
   acc[0] = hipmr_job_comb2<TMPL>(acc[0], acc[1]);
   acc[2] = hipmr_job_comb2<TMPL>(acc[2], acc[3]);
   float2 r = hipmr_job_comb2<TMPL>(acc[0], acc[2]);
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1)
-    r = hipmr_job_comb2<TMPL>(r, make_float2(__shfl_xor(r.x, m, 64), __shfl_xor(r.y, m, 64)));
+  r.x = hipmr_wave_fold(r.x, [](float p, float q) { return hipmr_job_comb<TMPL>(p, q); });
+  r.y = hipmr_wave_fold(r.y, [](float p, float q) { return p + q; });
   return r;
 }
 
@@ -257,9 +298,10 @@ __device__ __forceinline__ double2 hipmr_fin_comb(bool mx, double2 a, double2 b)
 }
 
 __device__ __forceinline__ double2 hipmr_fin_wave(bool mx, double2 v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1)
-    v = hipmr_fin_comb(mx, v, make_double2(__shfl_xor(v.x, m, 64), __shfl_xor(v.y, m, 64)));
+  const auto plus = [](double p, double q) { return p + q; };
+  v.x = mx ? hipmr_wave_fold(v.x, [](double p, double q) { return __builtin_elementwise_maximum(p, q); })
+           : hipmr_wave_fold(v.x, plus);
+  v.y = hipmr_wave_fold(v.y, plus);
   return v;
 }
 
@@ -503,11 +545,6 @@ extern "C" __global__ void __launch_bounds__(1024)
 // invalidate the whole L2 at every tile.)
 #define HIPMR_RING @@RING@@
 
-__device__ __forceinline__ unsigned long long hipmr_readlane64(unsigned long long v, int l) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
-  return (unsigned long long)hi << 32 | lo;
-}
 __device__ __forceinline__ unsigned long long hipmr_ld_agent(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -533,7 +570,9 @@ __device__ __forceinline__ hipmr_sjob hipmr_job_ld(const hipmr_sjob* p, bool sys
   for (int k = 0; k < 8; ++k) v[k] = system ? hipmr_ld_sys(w + k) : hipmr_ld_agent(w + k);
   // every lane read the same words: keep them in scalar registers
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = hipmr_readlane64(v[k], 0);
+  for (int k = 0; k < 8; ++k)
+    v[k] = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v[k] >> 32)) << 32 |
+           (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v[k]);
   hipmr_sjob J;
   __builtin_memcpy(&J, v, sizeof(J));
   return J;
@@ -580,7 +619,7 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const unsigned long 
       const unsigned long long v =
           lane < 63 ? hipmr_ld_sys(hr_words + ((seq + js) & (HIPMR_RING - 1)) * HIPMR_RING_WORDS + jw)
                     : hipmr_ld_sys(hdr + 16);
-      const unsigned long long Sw = __shfl(v, 63, 64);
+      const unsigned long long Sw = hipmr_readlane64(v, 63);
       // the stop word names the instance it is for (epoch << 44 | job index)
       const unsigned long long S = (Sw >> 44) == (epoch & ((1ull << 20) - 1)) ? (Sw & ((1ull << 44) - 1))
                                                                              : ~0ull;
@@ -624,7 +663,7 @@ __device__ void hipmr_res_dispatch(unsigned long long* hdr, const unsigned long 
           hipmr_st_agent(dtstart + slot, f[8]);
           tend = f[8] + (unsigned long long)hipmr_job_ntiles(J);
         }
-        tend = __shfl(tend, cnt - 1, 64);
+        tend = hipmr_readlane64(tend, cnt - 1);
         seq += cnt;
         hipmr_drain();                                   // the ring entries are written
         if (lane < 8)
@@ -843,9 +882,9 @@ extern "C" __global__ void __launch_bounds__(1024)
         while (todo) {
           const int hl = __builtin_ctzll(todo);
           todo &= todo - 1;
-          const unsigned long long fs = __shfl(s, hl, 64);
-          const int fg = __shfl(g, hl, 64);
-          const bool flocal = __shfl((int)local, hl, 64) != 0;
+          const unsigned long long fs = hipmr_readlane64(s, hl);
+          const int fg = __builtin_amdgcn_readlane(g, hl);
+          const bool flocal = __builtin_amdgcn_readlane((int)local, hl) != 0;
           const unsigned long long slot = fs & (HIPMR_RING - 1);
           const unsigned long long js = sh_js[hl];
           const int ntiles = sh_nt[hl], ng = (ntiles + 63) / 64, tmpl = sh_tm[hl];
@@ -865,7 +904,9 @@ extern "C" __global__ void __launch_bounds__(1024)
           bool last = ng == 1;
           double2 tot = gv;
           if (ng == 1) {
-            tot = hipmr_fin_level2(mx, lane == 0, gv, false, gv);
+            // level 2 over one group: only lane 0 holds a value, and folding
+            // the neutral elements of the other lanes into it changes no bit
+            tot = hipmr_fin_comb(mx, hipmr_fin_neutral(mx), gv);
           } else {
             if (lane == 0) {
               hipmr_st_agent(gpw + 2 * (slot * 128 + fg), __builtin_bit_cast(unsigned long long, gv.x));
@@ -878,7 +919,7 @@ extern "C" __global__ void __launch_bounds__(1024)
               if (o2 + 1 == (unsigned)ng)
                 __hip_atomic_store(jdone + slot, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            o2 = __shfl(o2, 0, 64);
+            o2 = __builtin_amdgcn_readlane(o2, 0);
             last = o2 + 1 == (unsigned)ng;
             if (last) {
               const bool h0 = lane < ng, h1 = lane + 64 < ng;
